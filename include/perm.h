@@ -1,0 +1,199 @@
+/*
+ * perm.h -- exact matrix permanents on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libpermgpu.so.  Every function is extern "C", takes plain pointers
+ * and sizes, never throws, and returns a perm_status (0 = success).
+ *
+ * What is computed (Masschelein, Richer & Ayers, "Optimizing and benchmarking
+ * the computation of the permanent of general matrices"):
+ *
+ *   per(A) = sum over injective maps s:[m]->[n] of prod_i a[i][s(i)], m <= n,
+ *   per(A) = per(A^T) when m > n,
+ *
+ * (Sec. 1.1, Eq. permanent_definition and Eq. rectangular_permanent_definition),
+ * and per(A) = 1 for m = 0 (empty product).  The three algorithms of Sec. 1.2
+ * all return this same value; they differ only in cost and rounding.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ *  - dA is a DEVICE pointer to a row-major m x n matrix with leading dimension
+ *    lda >= n, counted in elements of the input dtype (a PERM_C128 element is
+ *    16 bytes: real part then imaginary part).  m > n is served by reading the
+ *    transpose in place (no copy).
+ *  - dOut is a DEVICE pointer that receives one value of the requested output
+ *    type (see perm_out).  The caller owns dA and dOut; the library never
+ *    frees or retains them.
+ *  - stream is a hipStream_t (NULL = the default stream).  All device work is
+ *    enqueued on it and the call returns without waiting, with one exception:
+ *    integer outputs (PERM_OUT_I64 / PERM_OUT_I128) run an overflow pre-check
+ *    that reads per-row absolute sums back to the host and so synchronises the
+ *    stream, unless PERM_FLAG_WRAP is set.
+ *  - Temporary device memory (per-workgroup partial sums) is taken from the
+ *    stream-ordered allocator and released on the same stream; calls on
+ *    different streams do not share scratch memory and may run concurrently.
+ *  - Results are bitwise reproducible: partial sums are combined in a fixed
+ *    order that depends only on the shape and the device's compute-unit count.
+ *  - On any error nothing is written to dOut.
+ *
+ * Status codes
+ *   PERM_OK            success
+ *   PERM_E_INVALID     null pointer, lda < n, negative size, unknown enum,
+ *                      output type not valid for the input type
+ *   PERM_E_TOO_LARGE   the shape exceeds the algorithm's limit (stated with
+ *                      each function)
+ *   PERM_E_OVERFLOW    an integer output could exceed its type (pre-check bound
+ *                      prod_i sum_j |a_ij| >= 2^63 or 2^127) and PERM_FLAG_WRAP
+ *                      was not given, or an exact integer product could not be
+ *                      formed (an absolute row or column sum >= 2^53)
+ *   PERM_E_HIP         a HIP runtime call failed
+ *   PERM_E_UNSUPPORTED the combination of arguments is not implemented
+ */
+#ifndef PERM_H
+#define PERM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PERM_VERSION 10000 /* 1.0.0 */
+
+typedef enum perm_status {
+  PERM_OK = 0,
+  PERM_E_INVALID = -1,
+  PERM_E_TOO_LARGE = -2,
+  PERM_E_OVERFLOW = -3,
+  PERM_E_HIP = -4,
+  PERM_E_UNSUPPORTED = -5
+} perm_status;
+
+/* Input element type. */
+typedef enum perm_dtype {
+  PERM_F64 = 0,  /* double */
+  PERM_C128 = 1, /* complex double, interleaved (re, im) */
+  PERM_I64 = 2,  /* int64_t */
+  PERM_B8 = 3    /* uint8_t, every entry 0 or 1 (other values are read as 1) */
+} perm_dtype;
+
+/* Output type.  Valid pairs:
+ *   PERM_F64  input -> PERM_OUT_F64 or PERM_OUT_DD
+ *   PERM_C128 input -> PERM_OUT_C128 or PERM_OUT_CDD
+ *   PERM_I64 / PERM_B8 input -> PERM_OUT_I64, PERM_OUT_I128 (exact), or
+ *                                PERM_OUT_F64 / PERM_OUT_DD (floating-point path)
+ */
+typedef enum perm_out {
+  PERM_OUT_F64 = 0,  /* double */
+  PERM_OUT_C128 = 1, /* double[2] = (re, im) */
+  PERM_OUT_I64 = 2,  /* int64_t */
+  PERM_OUT_I128 = 3, /* {uint64_t lo; int64_t hi;} two's complement */
+  PERM_OUT_DD = 4,   /* double[2] = (hi, lo), value hi + lo, |lo| <= ulp(hi)/2 */
+  PERM_OUT_CDD = 5   /* double[4] = (re.hi, re.lo, im.hi, im.lo) */
+} perm_out;
+
+typedef enum perm_algo {
+  PERM_ALGO_COMBINATORIC = 0,
+  PERM_ALGO_RYSER = 1,
+  PERM_ALGO_GLYNN = 2
+} perm_algo;
+
+/* Flags (bitwise or). */
+#define PERM_FLAG_WRAP 0x1u /* integer outputs: skip the overflow pre-check and
+                               return the exact value modulo 2^64 / 2^128 (for
+                               Glynn: modulo 2^(128-(n-1)-v), v the power of two
+                               in (n-m)!), sign-extended */
+
+/* Library version, PERM_VERSION. */
+int perm_version(void);
+
+/* Static description of a status code (never NULL). */
+const char *perm_status_string(int status);
+
+/* Measurement support.  perm_profile_enable(1) makes every later single-matrix
+ * call record a pair of HIP events on its stream around its main kernel (the
+ * Gray-walk engine, the rectangular Ryser walk or the combinatoric kernel);
+ * perm_profile_last waits for the calling thread's most recent pair and
+ * returns the kernel's duration in milliseconds.  PERM_E_INVALID if no pair
+ * was recorded.  Off by default; costs two event records per call when on. */
+int perm_profile_enable(int on);
+int perm_profile_last(double *ms);
+
+/* perm_glynn -- Glynn's formula, Sec. 1.2 Eq. glynn:
+ *   per(A) = 2^-(n-1) sum_{delta in {+-1}^n, delta_1=+1} (prod delta) prod_j sum_i delta_i a_ij
+ * summed in reflected Gray-code order; for m < n the matrix is padded with
+ * n - m rows of ones and the sum divided by (n-m)! (Eq. glynn_filled_matrix,
+ * Eq. glynn_rectangle).  Cost 2^(n-1) terms of O(n), n = max(m, n).
+ * Limit: n <= 48 for floating-point outputs, n <= 40 for integer outputs. */
+int perm_glynn(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+               void *dOut, uint32_t flags, void *stream);
+
+/* perm_ryser -- Ryser's inclusion-exclusion formula, Sec. 1.2
+ * Eq. ryser_square (m = n) and Eq. ryser_rectangle (m < n, read over column
+ * subsets of size m-k with weight (-1)^k C(n-m+k, k)).  Square: Gray-code
+ * order over the 2^n column subsets; rectangular: the subsets of each size
+ * s <= m in revolving-door order.  Limits: square n <= 48 (floating point)
+ * or n <= 40 (integer); rectangular min(m, n) <= 40 and max(m, n) <= 64. */
+int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+               void *dOut, uint32_t flags, void *stream);
+
+/* perm_combinatoric -- the definition itself, one product per injective map
+ * (Sec. 1.2, cost m n!/(n-m)!).  Limit: n!/(n-m)! <= 2^40 maps. */
+int perm_combinatoric(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+                      void *dOut, uint32_t flags, void *stream);
+
+/* perm_auto -- picks one of the three algorithms from (m, n, density, dtype)
+ * with the learned selector if one is loaded (perm_selector_load), else with
+ * the threshold table modelled on the paper's Alg. 5 (App. B), and runs it.
+ * The value does not depend on the choice beyond rounding; integer outputs
+ * are identical.  *chosen (may be NULL) receives the algorithm used.
+ * density < 0 means "unknown" (treated as 1). */
+int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+              void *dOut, uint32_t flags, void *stream, double density, perm_algo *chosen);
+
+/* ---------------------------------------------------------------------- */
+/* Batched permanents                                                      */
+/* ---------------------------------------------------------------------- */
+/* A batch is `count` matrices inside one device buffer dData: matrix b is
+ * hM[b] x hN[b], row-major with leading dimension hLd[b] (elements), starting
+ * at element offset hOffset[b].  The shape arrays are HOST pointers, read
+ * during the call only.  dOut receives count values of the output type,
+ * contiguous.  One persistent launch serves the whole batch. */
+typedef struct perm_batch_plan perm_batch_plan;
+
+/* Build a plan (work list, scratch buffers) for a batch of shapes and an
+ * algorithm (PERM_ALGO_GLYNN, or PERM_ALGO_RYSER for square shapes).  The plan
+ * is bound to the current device.  *plan receives an owning handle. */
+int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
+                           const int64_t *hOffset, const int64_t *hLd, perm_dtype dt,
+                           perm_out ot, perm_algo algo, uint32_t flags, perm_batch_plan **plan);
+
+/* Run a plan on (dData, dOut).  The first run for a given (dData, dOut,
+ * stream) captures the launch sequence into a hipGraph owned by the plan;
+ * later runs with the same pointers replay it. */
+int perm_batch_plan_run(perm_batch_plan *plan, const void *dData, void *dOut, void *stream);
+
+/* Release the plan and its graph and scratch memory (NULL is ignored). */
+int perm_batch_plan_destroy(perm_batch_plan *plan);
+
+/* One-shot convenience: create, run (without graph capture), destroy. */
+int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
+                       const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
+                       void *dOut, uint32_t flags, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Algorithm selection                                                     */
+/* ---------------------------------------------------------------------- */
+/* Load selector weights written by perm_selector_save (text format).  path
+ * NULL unloads them (perm_auto then uses the threshold table). */
+int perm_selector_load(const char *path);
+
+/* The choice perm_auto would make, without running anything.  *source (may
+ * be NULL) receives 1 if the learned selector decided, 0 for the table. */
+int perm_select(int m, int n, perm_dtype dt, double density, perm_algo *chosen, int *source);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERM_H */

@@ -1,0 +1,110 @@
+// C ABI: the combinatoric path, algorithm selection (perm_auto / perm_select)
+// and the selector weight loader.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "runtime.h"
+#include "selector.h"
+
+using namespace permgpu;
+
+namespace permgpu {
+
+int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                     perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind) {
+  // number of injective maps N!/(N-M)!, limited to 2^40
+  u128_host total = 1;
+  for (int i = 0; i < M; ++i) {
+    total *= (u128_host)(N - i);
+    if (total > ((u128_host)1 << 40)) return PERM_E_TOO_LARGE;
+  }
+  if (kind == ENGINE_INT) {
+    int pl = 0;
+    int rc = int_precheck(1, M, N, dt, dA, lda, tr, ot, flags, s, pl);
+    if (rc == PERM_E_OVERFLOW && (flags & PERM_FLAG_WRAP)) rc = PERM_OK;  // exact mod 2^128
+    if (rc) return rc;
+  }
+  const int cus = device_cus();
+  if (cus <= 0) return PERM_E_HIP;
+  const uint64_t threads = (uint64_t)total;
+  int grid = (int)std::min<uint64_t>((uint64_t)cus * 8, (threads + 255) / 256);
+  grid = std::max(grid, 1);
+  const int C = kind == ENGINE_CPLX ? 2 : 1;
+  double *part = nullptr;
+  if (hipMallocAsync((void **)&part, sizeof(double) * 2 * C * (size_t)grid, s) != hipSuccess)
+    return PERM_E_HIP;
+  profile_begin(s);
+  hipError_t e = launch_combinatoric(kind, M, N, dt, dA, lda, tr, (uint64_t)total, grid, part, s);
+  profile_end(s);
+  if (e == hipSuccess) {
+    Finish f;
+    f.mode = FINISH_PLAIN;
+    f.m = M;
+    f.n = N;
+    f.ot = ot;
+    e = launch_finish(kind, part, grid, f, dOut, s);
+  }
+  hipError_t e2 = hipFreeAsync(part, s);
+  if (e == hipSuccess) e = e2;
+  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+}
+
+}  // namespace permgpu
+
+extern "C" {
+
+int perm_combinatoric(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+                      void *dOut, uint32_t flags, void *stream) {
+  int kind = 0;
+  int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int tr = m > n;
+  const int M = std::min(m, n), N = std::max(m, n);
+  if (M == 0) return launch_write_one(ot, dOut, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
+  if (N > kMaxN) return PERM_E_TOO_LARGE;
+  return run_combinatoric(M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind);
+}
+
+int perm_select(int m, int n, perm_dtype dt, double density, perm_algo *chosen, int *source) {
+  if (m < 0 || n < 0 || (int)dt < 0 || (int)dt > (int)PERM_B8) return PERM_E_INVALID;
+  const int M = std::min(m, n), N = std::max(m, n);
+  int src = 0;
+  perm_algo a = select_algorithm(M, N, dt, density, &src);
+  if (chosen) *chosen = a;
+  if (source) *source = src;
+  return PERM_OK;
+}
+
+int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,
+              uint32_t flags, void *stream, double density, perm_algo *chosen) {
+  int kind = 0;
+  int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
+  if (rc) return rc;
+  const int M = std::min(m, n), N = std::max(m, n);
+  int src = 0;
+  perm_algo a = select_algorithm(M, N, dt, density, &src);
+  // fall back along the cheaper algorithms if the choice cannot serve the shape
+  if (a == PERM_ALGO_COMBINATORIC) {
+    u128_host total = 1;
+    for (int i = 0; i < M; ++i) total *= (u128_host)(N - i);
+    if (total > ((u128_host)1 << 40)) a = PERM_ALGO_GLYNN;
+  }
+  if (a == PERM_ALGO_GLYNN && kind == ENGINE_INT && N > 28 && M < N) a = PERM_ALGO_RYSER;
+  if (a == PERM_ALGO_GLYNN && N > ENGINE_MAX_NV_REAL) a = PERM_ALGO_RYSER;
+  if (chosen) *chosen = a;
+  switch (a) {
+    case PERM_ALGO_COMBINATORIC:
+      return perm_combinatoric(m, n, dt, dA, lda, ot, dOut, flags, stream);
+    case PERM_ALGO_RYSER: return perm_ryser(m, n, dt, dA, lda, ot, dOut, flags, stream);
+    default: return perm_glynn(m, n, dt, dA, lda, ot, dOut, flags, stream);
+  }
+}
+
+int perm_selector_load(const char *path) { return selector_load_file(path); }
+
+}  // extern "C"

@@ -1,0 +1,397 @@
+// C ABI of libpermgpu: argument validation, orientation, the integer
+// overflow pre-check, launch planning and scratch management.  Every step of
+// the computation runs in the HIP kernels; this file only plans and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+#include "runtime.h"
+
+using namespace permgpu;
+
+namespace permgpu {
+
+// ------------------------------------------------------------------ //
+// device properties (cached per device)                               //
+// ------------------------------------------------------------------ //
+int device_cus() {
+  static std::mutex mu;
+  static std::vector<int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (cache[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    cache[dev] = cus;
+  }
+  return cache[dev];
+}
+
+static int env_int(const char *name, int dflt) {
+  const char *v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atoi(v);
+}
+
+static uint64_t pow2_floor(uint64_t x) {
+  uint64_t p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+static int ilog2(uint64_t x) {
+  int r = 0;
+  while (x > 1) { x >>= 1; ++r; }
+  return r;
+}
+
+// ------------------------------------------------------------------ //
+// optional engine-kernel timing (perm_profile_enable / perm_profile_last)  //
+// ------------------------------------------------------------------ //
+static std::atomic<int> g_profile{0};
+struct ProfileSlot {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool valid = false;
+};
+static thread_local ProfileSlot t_prof;
+
+void profile_begin(hipStream_t s) {
+  if (!g_profile.load()) return;
+  if (!t_prof.a) {
+    if (hipEventCreate(&t_prof.a) != hipSuccess || hipEventCreate(&t_prof.b) != hipSuccess) return;
+  }
+  t_prof.valid = hipEventRecord(t_prof.a, s) == hipSuccess;
+}
+void profile_end(hipStream_t s) {
+  if (!g_profile.load() || !t_prof.valid) return;
+  t_prof.valid = hipEventRecord(t_prof.b, s) == hipSuccess;
+}
+
+// ------------------------------------------------------------------ //
+// launch planning for the Gray-code engine                           //
+// ------------------------------------------------------------------ //
+int plan_gray(int kind, int nv, int nbits, GrayPlan &p) {
+  int bpc = 0;
+  switch (kind) {
+    case ENGINE_REAL: bpc = gray_engine_blocks_per_cu_real(nv); break;
+    case ENGINE_CPLX: bpc = gray_engine_blocks_per_cu_cplx(nv); break;
+    default: bpc = gray_engine_blocks_per_cu_int(nv); break;
+  }
+  const int cus = device_cus();
+  if (bpc <= 0 || cus <= 0) return PERM_E_HIP;
+  const uint64_t lanes_max = pow2_floor((uint64_t)cus * (uint64_t)bpc * 256u);
+  const int lg = ilog2(lanes_max);
+  int b;
+  if (nbits == 0) {
+    b = 0;
+  } else {
+    // enough blocks per lane to amortise the tail, blocks of at most 2^10
+    // steps between closed-form re-seeds
+    b = nbits - lg - 4;
+    b = std::max(1, std::min(b, 10));
+    const int bo = env_int("PERM_BLOCK_LOG2", -1);
+    if (bo >= 1) b = bo;
+    b = std::min(b, nbits);
+  }
+  const uint64_t L = 1ull << (nbits - b);
+  uint64_t lanes, bpl;
+  if (L == 1) {
+    lanes = 1;
+    bpl = 1;
+  } else {
+    lanes = std::min<uint64_t>(lanes_max, L / 2);
+    bpl = L / lanes;  // even
+  }
+  p.b = b;
+  p.lanes = lanes;
+  p.blocks_per_lane = bpl;
+  p.block = (int)std::min<uint64_t>(256, lanes);
+  p.grid = (int)(lanes / (uint64_t)p.block);
+  return PERM_OK;
+}
+
+// ------------------------------------------------------------------ //
+// integer pre-check: bounds on |v_j| and on |per|                     //
+// ------------------------------------------------------------------ //
+static u128_host sat_mul(u128_host a, u128_host b) {
+  if (a == 0 || b == 0) return 0;
+  const u128_host lim = ~(u128_host)0;
+  if (a > lim / b) return lim;
+  return a * b;
+}
+
+// Largest product-tree depth PL in {3,2,1,0} such that every chunk of 2^PL
+// consecutive factors has a bound product below 2^53; -1 if a single factor
+// can reach 2^53.
+static int product_levels(const std::vector<uint64_t> &bounds) {
+  const u128_host lim = (u128_host)1 << 53;
+  for (uint64_t b : bounds)
+    if ((u128_host)b >= lim) return -1;
+  for (int pl = 3; pl >= 0; --pl) {
+    const size_t c = (size_t)1 << pl;
+    bool ok = true;
+    for (size_t s = 0; s < bounds.size() && ok; s += c) {
+      u128_host prod = 1;
+      for (size_t i = s; i < std::min(bounds.size(), s + c); ++i) prod = sat_mul(prod, bounds[i]);
+      if (prod >= lim) ok = false;
+    }
+    if (ok) return pl;
+  }
+  return 0;
+}
+
+static int read_abs_sums(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                         int by_cols, std::vector<uint64_t> &out, hipStream_t s) {
+  const int count = (by_cols == 1 || by_cols == 3) ? N : M;
+  out.assign(count, 0);
+  uint64_t *d = nullptr;
+  if (hipMallocAsync((void **)&d, sizeof(uint64_t) * (size_t)count, s) != hipSuccess)
+    return PERM_E_HIP;
+  hipError_t e = launch_abs_sums(M, N, dt, dA, lda, tr, by_cols, d, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out.data(), d, sizeof(uint64_t) * (size_t)count, hipMemcpyDeviceToHost, s);
+  hipError_t e2 = hipFreeAsync(d, s);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+}
+
+// Fills `pl` and checks overflow for an integer run of `algo` (0 Glynn,
+// 1 Ryser square/rect) on the logical M x N matrix.
+int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                 perm_out ot, uint32_t flags, hipStream_t s, int &pl) {
+  const bool wrap = (flags & PERM_FLAG_WRAP) != 0;
+  std::vector<uint64_t> rows, cols;
+  if (dt == PERM_B8 && wrap) {
+    rows.assign(M, (uint64_t)N);
+    cols.assign(N, (uint64_t)N);
+  } else {
+    int rc = read_abs_sums(M, N, dt, dA, lda, tr, 0, rows, s);
+    if (rc) return rc;
+    if (algo == 0) {
+      rc = read_abs_sums(M, N, dt, dA, lda, tr, 1, cols, s);
+      if (rc) return rc;
+      for (auto &c : cols) c = (c > ~0ull - (uint64_t)N) ? ~0ull : c + (uint64_t)(N - M);
+    }
+  }
+  pl = product_levels(algo == 0 ? cols : rows);
+  if (pl < 0) return PERM_E_OVERFLOW;
+  if (wrap) return PERM_OK;
+  // log2 of an upper bound on |per(A)| <= per(|A|):
+  //   any matrix:  prod_i sum_j |a_ij|  (each row sum bounds that row's choices)
+  //   0/1 matrix:  Bregman's theorem on the square 0/1 matrix A' = [A; J] padded
+  //                with N-M rows of ones, per(A') = (N-M)! per(A) and
+  //                per(A') <= prod_rows (r!)^(1/r).
+  double lg = 0.0;
+  for (uint64_t r : rows) {
+    if (r == 0) return PERM_OK;  // a zero row: per = 0
+    lg += std::log2((double)r);
+  }
+  if (M == N) {
+    // Carlen-Lieb-Loss: |per(A)| <= n!/n^(n/2) prod_j ||a_j||_2 over the columns
+    // (and, applied to A^T, over the rows)
+    std::vector<uint64_t> sq_rows, sq_cols;
+    int rc = read_abs_sums(M, N, dt, dA, lda, tr, 2, sq_rows, s);
+    if (!rc) rc = read_abs_sums(M, N, dt, dA, lda, tr, 3, sq_cols, s);
+    if (rc) return rc;
+    const double base = std::lgamma((double)N + 1.0) / std::log(2.0) -
+                        0.5 * (double)N * std::log2((double)N);
+    double lr = base, lc = base;
+    for (int i = 0; i < N; ++i) {
+      double qr, qc;
+      std::memcpy(&qr, &sq_rows[i], 8);
+      std::memcpy(&qc, &sq_cols[i], 8);
+      // each sum of squares is rounded (relative error below N u)
+      lr += 0.5 * std::log2(qr * (1.0 + 1e-12));
+      lc += 0.5 * std::log2(qc * (1.0 + 1e-12));
+    }
+    lg = std::min(lg, std::min(lr, lc));
+  }
+  if (dt == PERM_B8) {
+    double lb = 0.0;
+    for (uint64_t r : rows) lb += std::lgamma((double)r + 1.0) / std::log(2.0) / (double)r;
+    lb += (double)(N - M) * std::lgamma((double)N + 1.0) / std::log(2.0) / (double)N;
+    lb -= std::lgamma((double)(N - M) + 1.0) / std::log(2.0);
+    lg = std::min(lg, lb);
+  }
+  lg = lg * (1.0 + 1e-12) + 1e-9;  // margin for rounding in the logarithms
+  if (ot == PERM_OUT_I64 && lg >= 63.0) return PERM_E_OVERFLOW;
+  if (lg >= 127.0) return PERM_E_OVERFLOW;
+  if (algo == 0) {
+    // the Glynn sum itself is 2^(N-1) (N-M)! per(A)
+    double lx = lg + (double)(N - 1) + std::lgamma((double)(N - M) + 1.0) / std::log(2.0);
+    if (lx >= 127.0) return PERM_E_OVERFLOW;
+  }
+  return PERM_OK;
+}
+
+// ------------------------------------------------------------------ //
+// validation                                                          //
+// ------------------------------------------------------------------ //
+int engine_kind_for(perm_dtype dt, perm_out ot, int &kind) {
+  switch (dt) {
+    case PERM_F64:
+      if (ot != PERM_OUT_F64 && ot != PERM_OUT_DD) return PERM_E_INVALID;
+      kind = ENGINE_REAL;
+      return PERM_OK;
+    case PERM_C128:
+      if (ot != PERM_OUT_C128 && ot != PERM_OUT_CDD) return PERM_E_INVALID;
+      kind = ENGINE_CPLX;
+      return PERM_OK;
+    case PERM_I64:
+    case PERM_B8:
+      if (ot == PERM_OUT_I64 || ot == PERM_OUT_I128) kind = ENGINE_INT;
+      else if (ot == PERM_OUT_F64 || ot == PERM_OUT_DD) kind = ENGINE_REAL;
+      else return PERM_E_INVALID;
+      return PERM_OK;
+    default:
+      return PERM_E_INVALID;
+  }
+}
+
+int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,
+             int &kind) {
+  if (m < 0 || n < 0 || dOut == nullptr) return PERM_E_INVALID;
+  if ((int)ot < 0 || (int)ot > (int)PERM_OUT_CDD) return PERM_E_INVALID;
+  int rc = engine_kind_for(dt, ot, kind);
+  if (rc) return rc;
+  if (m > 0 && n > 0) {
+    if (dA == nullptr || lda < n) return PERM_E_INVALID;
+  }
+  return PERM_OK;
+}
+
+// ------------------------------------------------------------------ //
+// the Gray-walk path (Glynn square/rectangular, Ryser square)        //
+// ------------------------------------------------------------------ //
+int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+             perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind) {
+  // algo 0: Glynn (NV = N, nbits = N-1); algo 1: square Ryser (NV = M = N, nbits = N)
+  const int nv = algo == 0 ? N : M;
+  const int nbits = algo == 0 ? N - 1 : N;
+  const int nv_max = kind == ENGINE_REAL ? ENGINE_MAX_NV_REAL
+                     : kind == ENGINE_CPLX ? ENGINE_MAX_NV_CPLX
+                                           : ENGINE_MAX_NV_INT;
+  if (nv > nv_max) return PERM_E_TOO_LARGE;
+  int pl = 3;
+  if (kind == ENGINE_INT) {
+    int rc = int_precheck(algo, M, N, dt, dA, lda, tr, ot, flags, s, pl);
+    if (rc) return rc;
+  }
+  GrayPlan plan;
+  int rc = plan_gray(kind, nv, nbits, plan);
+  if (rc) return rc;
+  const int C = kind == ENGINE_CPLX ? 2 : 1;
+  const size_t tbl_n = (size_t)2 * nbits * nv * C;
+  const size_t base_n = (size_t)nv * C;
+  const size_t part_n = (size_t)plan.grid * 2 * C;
+  const size_t bytes = sizeof(double) * (tbl_n + base_n + part_n) + 256;
+  char *scratch = nullptr;
+  if (hipMallocAsync((void **)&scratch, bytes, s) != hipSuccess) return PERM_E_HIP;
+  double *tbl = (double *)scratch;
+  double *base = tbl + tbl_n;
+  double *part = base + base_n;
+  hipError_t e = launch_stage_gray(algo, M, N, dt, dA, lda, tr, tbl, base, C == 2, s);
+  if (e == hipSuccess) {
+    GrayWalk w;
+    w.tbl = tbl;
+    w.base = base;
+    w.nv = nv;
+    w.nbits = nbits;
+    w.b = plan.b;
+    w.prod_levels = pl;
+    w.blocks_per_lane = plan.blocks_per_lane;
+    profile_begin(s);
+    switch (kind) {
+      case ENGINE_REAL: e = launch_gray_engine_real(w, plan.grid, plan.block, part, s); break;
+      case ENGINE_CPLX: e = launch_gray_engine_cplx(w, plan.grid, plan.block, part, s); break;
+      default: e = launch_gray_engine_int(w, plan.grid, plan.block, part, s); break;
+    }
+    profile_end(s);
+  }
+  if (e == hipSuccess) {
+    Finish f;
+    f.mode = algo == 0 ? FINISH_GLYNN : FINISH_RYSER_SQ;
+    f.m = M;
+    f.n = N;
+    f.ot = ot;
+    e = launch_finish(kind, part, plan.grid, f, dOut, s);
+  }
+  hipError_t e2 = hipFreeAsync(scratch, s);
+  if (e == hipSuccess) e = e2;
+  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+}
+
+}  // namespace permgpu
+
+// ==================================================================== //
+// public entry points                                                  //
+// ==================================================================== //
+extern "C" {
+
+int perm_version(void) { return PERM_VERSION; }
+
+int perm_profile_enable(int on) {
+  g_profile.store(on ? 1 : 0);
+  return PERM_OK;
+}
+
+int perm_profile_last(double *ms) {
+  if (!ms) return PERM_E_INVALID;
+  if (!t_prof.valid) return PERM_E_INVALID;
+  if (hipEventSynchronize(t_prof.b) != hipSuccess) return PERM_E_HIP;
+  float f = 0.f;
+  if (hipEventElapsedTime(&f, t_prof.a, t_prof.b) != hipSuccess) return PERM_E_HIP;
+  *ms = (double)f;
+  return PERM_OK;
+}
+
+const char *perm_status_string(int status) {
+  switch (status) {
+    case PERM_OK: return "success";
+    case PERM_E_INVALID: return "invalid argument";
+    case PERM_E_TOO_LARGE: return "matrix too large for this algorithm";
+    case PERM_E_OVERFLOW: return "integer result may overflow the output type";
+    case PERM_E_HIP: return "HIP runtime error";
+    case PERM_E_UNSUPPORTED: return "unsupported combination of arguments";
+    default: return "unknown status";
+  }
+}
+
+int perm_glynn(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,
+               uint32_t flags, void *stream) {
+  int kind = 0;
+  int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int tr = m > n;
+  const int M = std::min(m, n), N = std::max(m, n);
+  if (M == 0) return launch_write_one(ot, dOut, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
+  if (N > kMaxN) return PERM_E_TOO_LARGE;
+  return run_gray(0, M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind);
+}
+
+int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,
+               uint32_t flags, void *stream) {
+  int kind = 0;
+  int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int tr = m > n;
+  const int M = std::min(m, n), N = std::max(m, n);
+  if (M == 0) return launch_write_one(ot, dOut, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
+  if (N > kMaxN) return PERM_E_TOO_LARGE;
+  if (M == N) return run_gray(1, M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind);
+  return run_ryser_rect(M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind);
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Routes a Gray-walk launch to the translation unit that instantiates its
+// vector length.
+#include "internal.h"
+
+namespace permgpu {
+
+int gray_occ_real_a(int nv);
+hipError_t gray_launch_real_a(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_real_b(int nv);
+hipError_t gray_launch_real_b(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_real_c(int nv);
+hipError_t gray_launch_real_c(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_cplx_a(int nv);
+hipError_t gray_launch_cplx_a(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_cplx_b(int nv);
+hipError_t gray_launch_cplx_b(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_cplx_c(int nv);
+hipError_t gray_launch_cplx_c(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_int_a(int nv);
+hipError_t gray_launch_int_a(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_int_b(int nv);
+hipError_t gray_launch_int_b(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_int_c(int nv);
+hipError_t gray_launch_int_c(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_int_d(int nv);
+hipError_t gray_launch_int_d(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+
+int gray_engine_blocks_per_cu_real(int nv) {
+  if (nv >= 1 && nv <= 24) return gray_occ_real_a(nv);
+  if (nv >= 25 && nv <= 40) return gray_occ_real_b(nv);
+  if (nv >= 41 && nv <= 48) return gray_occ_real_c(nv);
+  return 0;
+}
+
+hipError_t launch_gray_engine_real(const GrayWalk &w, int grid, int block, void *partials,
+                                   hipStream_t s) {
+  if (w.nv >= 1 && w.nv <= 24) return gray_launch_real_a(w, grid, block, partials, s);
+  if (w.nv >= 25 && w.nv <= 40) return gray_launch_real_b(w, grid, block, partials, s);
+  if (w.nv >= 41 && w.nv <= 48) return gray_launch_real_c(w, grid, block, partials, s);
+  return hipErrorInvalidValue;
+}
+
+int gray_engine_blocks_per_cu_cplx(int nv) {
+  if (nv >= 1 && nv <= 24) return gray_occ_cplx_a(nv);
+  if (nv >= 25 && nv <= 40) return gray_occ_cplx_b(nv);
+  if (nv >= 41 && nv <= 48) return gray_occ_cplx_c(nv);
+  return 0;
+}
+
+hipError_t launch_gray_engine_cplx(const GrayWalk &w, int grid, int block, void *partials,
+                                   hipStream_t s) {
+  if (w.nv >= 1 && w.nv <= 24) return gray_launch_cplx_a(w, grid, block, partials, s);
+  if (w.nv >= 25 && w.nv <= 40) return gray_launch_cplx_b(w, grid, block, partials, s);
+  if (w.nv >= 41 && w.nv <= 48) return gray_launch_cplx_c(w, grid, block, partials, s);
+  return hipErrorInvalidValue;
+}
+
+int gray_engine_blocks_per_cu_int(int nv) {
+  if (nv >= 1 && nv <= 16) return gray_occ_int_a(nv);
+  if (nv >= 17 && nv <= 26) return gray_occ_int_b(nv);
+  if (nv >= 27 && nv <= 34) return gray_occ_int_c(nv);
+  if (nv >= 35 && nv <= 40) return gray_occ_int_d(nv);
+  return 0;
+}
+
+hipError_t launch_gray_engine_int(const GrayWalk &w, int grid, int block, void *partials,
+                                   hipStream_t s) {
+  if (w.nv >= 1 && w.nv <= 16) return gray_launch_int_a(w, grid, block, partials, s);
+  if (w.nv >= 17 && w.nv <= 26) return gray_launch_int_b(w, grid, block, partials, s);
+  if (w.nv >= 27 && w.nv <= 34) return gray_launch_int_c(w, grid, block, partials, s);
+  if (w.nv >= 35 && w.nv <= 40) return gray_launch_int_d(w, grid, block, partials, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace permgpu

@@ -1,0 +1,8 @@
+// Gray-code engine instantiations: real kind, vector lengths 1..24.
+#include "internal.h"
+#define GRAY_KIND ENGINE_REAL
+#define GRAY_NV_LO 1
+#define GRAY_NV_HI 24
+#define GRAY_OCC_NAME gray_occ_real_a
+#define GRAY_LAUNCH_NAME gray_launch_real_a
+#include "gray_engine.inc"

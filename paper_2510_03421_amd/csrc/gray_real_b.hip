@@ -1,0 +1,8 @@
+// Gray-code engine instantiations: real kind, vector lengths 25..40.
+#include "internal.h"
+#define GRAY_KIND ENGINE_REAL
+#define GRAY_NV_LO 25
+#define GRAY_NV_HI 40
+#define GRAY_OCC_NAME gray_occ_real_b
+#define GRAY_LAUNCH_NAME gray_launch_real_b
+#include "gray_engine.inc"

@@ -1,0 +1,8 @@
+// Gray-code engine instantiations: real kind, vector lengths 41..48.
+#include "internal.h"
+#define GRAY_KIND ENGINE_REAL
+#define GRAY_NV_LO 41
+#define GRAY_NV_HI 48
+#define GRAY_OCC_NAME gray_occ_real_c
+#define GRAY_LAUNCH_NAME gray_launch_real_c
+#include "gray_engine.inc"

@@ -1,0 +1,120 @@
+// Internal declarations shared by the host runtime (capi.cpp) and the HIP
+// kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/perm.h"
+
+namespace permgpu {
+
+constexpr int kMaxN = 64;        // largest side accepted by any path
+
+// Largest Gray-walk vector length per engine kind (the instantiated range).
+#define ENGINE_MAX_NV_REAL 48
+#define ENGINE_MAX_NV_CPLX 48
+#define ENGINE_MAX_NV_INT 40
+#ifndef RECT_MAX_M
+#define RECT_MAX_M 40
+#endif
+constexpr int kReduceThreads = 256;
+
+// Element kind of the Gray-code engine.
+enum EngineKind : int {
+  ENGINE_REAL = 0,  // binary64 sums, double-double accumulation
+  ENGINE_CPLX = 1,  // complex binary64 sums, complex double-double accumulation
+  ENGINE_INT = 2    // integer-valued binary64 sums (exact), products and sums mod 2^128
+};
+
+// How the engine's raw signed sum E = sum_k (-1)^k prod_j v_j(k) becomes the
+// permanent.
+enum FinishMode : int {
+  FINISH_GLYNN = 0,     // per = E / (2^(n-1) (n-m)!)
+  FINISH_RYSER_SQ = 1,  // per = (-1)^n E
+  FINISH_PLAIN = 2      // per = E (weights already applied)
+};
+
+// A Gray-code walk: vector v of NV entries indexed by k in [0, 2^nbits).
+//   v(0) = base,   bit q of g(k) = k ^ (k>>1) set  <=>  U[q] added.
+// The update table holds, for each bit q, +U[q] (d = 0) and -U[q] (d = 1),
+// at tbl[(2q + d) * NV * C + j * C + c] with C = 1 (real) or 2 (complex).
+struct GrayWalk {
+  const double *tbl;   // device, (2 * nbits) * NV * C doubles
+  const double *base;  // device, NV * C doubles
+  int nv;              // vector length
+  int nbits;           // number of Gray bits (terms = 2^nbits)
+  int b;               // log2 of the per-lane block length
+  int prod_levels;     // ENGINE_INT only: exact binary64 product-tree depth
+  uint64_t blocks_per_lane;
+};
+
+// Rectangular Ryser by subset size (see ryser_rect.hip for the layout).
+struct RectWalk {
+  const double *colT;      // n columns of m (x C) doubles: colT[(j*m + i)*C + c]
+  const double *D;         // l*l difference columns D[out*l + in] = col[in] - col[out]
+  const uint32_t *trans;   // revolving-door transitions (out*l + in), all k-walks
+  const uint32_t *meta32;  // k_lo[65], k_hi[65], trans offsets[66], start masks[65]
+  const uint64_t *meta64;  // class cost0/item cost/items/lanes [65 each], w(s) int64/double
+  const uint64_t *binom;   // C(x, t) for x, t <= 64, at [x*65 + t]
+  int m, n, l, h;
+  int a_lo, a_hi;
+  int prod_levels;
+  uint64_t total_cost;
+};
+
+struct Finish {
+  int mode;       // FinishMode
+  int m, n;       // logical shape after orientation (m <= n)
+  perm_out ot;
+};
+
+// ---- launchers (each returns a hipError_t) ----
+// Stage A into the update table of a Glynn walk (padded rows of ones for m<n)
+// or a square Ryser walk; converts the input dtype; `tr` reads A^T.
+hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
+                             int tr, double *tbl, double *base, int cplx, hipStream_t s);
+
+// Engine: one partial per workgroup into `partials` (real: 2 doubles,
+// complex: 4 doubles, int: 2 uint64).  The walk's vector length w.nv must be
+// at most ENGINE_MAX_NV_{REAL,CPLX,INT}.
+hipError_t launch_gray_engine_real(const GrayWalk &w, int grid, int block, void *partials,
+                                   hipStream_t s);
+hipError_t launch_gray_engine_cplx(const GrayWalk &w, int grid, int block, void *partials,
+                                   hipStream_t s);
+hipError_t launch_gray_engine_int(const GrayWalk &w, int grid, int block, void *partials,
+                                  hipStream_t s);
+// Resident 256-thread workgroups per CU for an engine instantiation (0 = none).
+int gray_engine_blocks_per_cu_real(int nv);
+int gray_engine_blocks_per_cu_cplx(int nv);
+int gray_engine_blocks_per_cu_int(int nv);
+
+// Single-workgroup deterministic reduction of `count` partials, scaling, and
+// the typed write of the result.
+hipError_t launch_finish(int kind, const void *partials, int count, const Finish &f, void *dOut,
+                         hipStream_t s);
+
+// Magnitudes of each logical row (by_cols = 0) or column (1) of an integer
+// matrix: absolute sums, exact, saturating at 2^64 - 1; by_cols = 2 / 3: sums
+// of squares of each row / column as doubles (bit patterns).
+hipError_t launch_abs_sums(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                           int by_cols, uint64_t *dSums, hipStream_t s);
+
+// Rectangular Ryser staging (column table and difference columns) and engine.
+hipError_t launch_stage_rect(int m, int n, int l, perm_dtype dt, const void *dA, int64_t lda,
+                             int tr, double *colT, double *D, int cplx, hipStream_t s);
+hipError_t launch_ryser_rect(int kind, const RectWalk &w, int grid, void *partials,
+                             hipStream_t s);
+hipError_t launch_ryser_rect_real(const RectWalk &w, int grid, void *partials, hipStream_t s);
+hipError_t launch_ryser_rect_cplx(const RectWalk &w, int grid, void *partials, hipStream_t s);
+hipError_t launch_ryser_rect_int(const RectWalk &w, int grid, void *partials, hipStream_t s);
+
+// The definition: `total` = n!/(n-m)! maps split over grid x 256 threads, one
+// partial per workgroup.
+hipError_t launch_combinatoric(int kind, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
+                               int tr, uint64_t total, int grid, void *partials, hipStream_t s);
+
+// Writes the value 1 in the output type (the permanent of an empty matrix).
+hipError_t launch_write_one(perm_out ot, void *dOut, hipStream_t s);
+
+}  // namespace permgpu

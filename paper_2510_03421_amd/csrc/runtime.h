@@ -1,0 +1,42 @@
+// Host-side runtime declarations of libpermgpu (planning, pre-checks, the
+// per-algorithm runners).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace permgpu {
+
+typedef unsigned __int128 u128_host;
+
+struct GrayPlan {
+  int b;                     // log2 of the per-lane block length (re-seed period)
+  uint64_t lanes;            // lanes launched (a power of two)
+  uint64_t blocks_per_lane;  // blocks walked by each lane (even, or 1 when lanes = 1)
+  int block, grid;           // workgroup size and count
+};
+
+int device_cus();
+// engine-kernel timing around one launch (no-ops unless perm_profile_enable(1))
+void profile_begin(hipStream_t s);
+void profile_end(hipStream_t s);
+int plan_gray(int kind, int nv, int nbits, GrayPlan &p);
+int engine_kind_for(perm_dtype dt, perm_out ot, int &kind);
+int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,
+             int &kind);
+int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                 perm_out ot, uint32_t flags, hipStream_t s, int &pl);
+
+// Runners on the logical M x N matrix (M <= N; tr = read A^T).
+int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+             perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
+int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                     perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
+int run_ryser_rect(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
+                   void *dOut, uint32_t flags, hipStream_t s, int kind);
+
+}  // namespace permgpu

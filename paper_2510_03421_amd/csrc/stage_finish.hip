@@ -1,0 +1,324 @@
+// Staging of the input into Gray-walk update tables, the deterministic final
+// reduction with the per-algorithm normalisation, and the absolute-sum pass of
+// the integer overflow pre-check.
+#include "device_common.h"
+#include "internal.h"
+
+namespace permgpu {
+namespace {
+
+// Read logical entry (i, j) of A (m <= n after orientation) as (re, im).
+__device__ __forceinline__ void read_entry(perm_dtype dt, const void *dA, int64_t lda, int tr,
+                                           int i, int j, double &re, double &im) {
+  const int64_t o = tr ? (int64_t)j * lda + i : (int64_t)i * lda + j;
+  im = 0.0;
+  switch (dt) {
+    case PERM_F64: re = ((const double *)dA)[o]; break;
+    case PERM_C128:
+      re = ((const double *)dA)[2 * o];
+      im = ((const double *)dA)[2 * o + 1];
+      break;
+    case PERM_I64: re = (double)((const int64_t *)dA)[o]; break;
+    default: re = ((const uint8_t *)dA)[o] ? 1.0 : 0.0; break;
+  }
+}
+
+// algo 0 (Glynn): NV = n, nbits = n-1, padded matrix a' (rows m..n-1 are ones),
+//   base_j = sum_i a'_ij, U[q]_j = -2 a'_{q+1, j}.
+// algo 1 (square Ryser): NV = m, nbits = n, base = 0, U[q]_i = a_{i, q}.
+__global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const void *dA,
+                                  int64_t lda, int tr, double *tbl, double *base, int C) {
+  const int nv = algo == 0 ? n : m;
+  const int nbits = algo == 0 ? n - 1 : n;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < nbits * nv) {
+    const int q = idx / nv, j = idx % nv;
+    double re, im;
+    if (algo == 0) {
+      if (q + 1 < m) {
+        read_entry(dt, dA, lda, tr, q + 1, j, re, im);
+      } else {
+        re = 1.0;
+        im = 0.0;
+      }
+      re *= -2.0;
+      im *= -2.0;
+    } else {
+      read_entry(dt, dA, lda, tr, j, q, re, im);
+    }
+    double *p = tbl + (size_t)(2 * q) * nv * C + (size_t)j * C;
+    double *mneg = tbl + (size_t)(2 * q + 1) * nv * C + (size_t)j * C;
+    p[0] = re;
+    mneg[0] = -re;
+    if (C == 2) {
+      p[1] = im;
+      mneg[1] = -im;
+    }
+  }
+  if (idx < nv) {
+    double sr = 0.0, si = 0.0;
+    if (algo == 0) {
+      for (int i = 0; i < n; ++i) {
+        double re = 1.0, im = 0.0;
+        if (i < m) read_entry(dt, dA, lda, tr, i, idx, re, im);
+        sr += re;
+        si += im;
+      }
+    }
+    base[(size_t)idx * C] = sr;
+    if (C == 2) base[(size_t)idx * C + 1] = si;
+  }
+}
+
+// ---- final reduction (one workgroup of kReduceThreads) ----
+__device__ __forceinline__ int v2_factorial(int k) {
+  int v = 0;
+  for (int q = 2; q <= k; ++q) {
+    int x = q;
+    while ((x & 1) == 0) { ++v; x >>= 1; }
+  }
+  return v;
+}
+
+__device__ u128 inverse_mod_2_128(u128 a) {  // a odd
+  u128 x = a;  // correct to 3 bits
+  for (int i = 0; i < 6; ++i) x = x * ((u128)2 - a * x);
+  return x;
+}
+
+__device__ void write_real(perm_out ot, double hi, double lo, void *out) {
+  double h, l;
+  fast_two_sum(hi, lo, h, l);
+  if (ot == PERM_OUT_DD) {
+    ((double *)out)[0] = h;
+    ((double *)out)[1] = l;
+  } else {
+    ((double *)out)[0] = h;
+  }
+}
+
+__global__ __launch_bounds__(kReduceThreads) void finish_kernel(int kind, const void *partials,
+                                                                int count, Finish f, void *out) {
+  __shared__ double sh[kReduceThreads][4];
+  __shared__ uint64_t si[kReduceThreads][2];
+  const int t = threadIdx.x;
+  if (kind == ENGINE_INT) {
+    u128 x = 0;
+    const uint64_t *p = (const uint64_t *)partials;
+    for (int i = t; i < count; i += kReduceThreads) x += ((u128)p[2 * i + 1]) << 64 | p[2 * i];
+    si[t][0] = (uint64_t)x;
+    si[t][1] = (uint64_t)(x >> 64);
+    __syncthreads();
+    for (int off = kReduceThreads / 2; off > 0; off >>= 1) {
+      if (t < off) {
+        u128 a = ((u128)si[t][1]) << 64 | si[t][0];
+        u128 b = ((u128)si[t + off][1]) << 64 | si[t + off][0];
+        a += b;
+        si[t][0] = (uint64_t)a;
+        si[t][1] = (uint64_t)(a >> 64);
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      u128 E = ((u128)si[0][1]) << 64 | si[0][0];
+      i128 per;
+      if (f.mode == FINISH_GLYNN) {
+        const int k = f.n - f.m;
+        const int v = v2_factorial(k);
+        u128 odd = 1;
+        for (int q = 2; q <= k; ++q) {
+          int x = q;
+          while ((x & 1) == 0) x >>= 1;
+          odd *= (u128)x;
+        }
+        const int K = f.n - 1 + v;
+        u128 y = K >= 128 ? 0 : (E >> K);             // (odd * per) mod 2^(128-K)
+        y = y * inverse_mod_2_128(odd);               // per mod 2^(128-K)
+        const int sh_ = K;                           // sign-extend from bit 127-K
+        per = sh_ == 0 ? (i128)y : ((i128)(y << sh_)) >> sh_;
+      } else if (f.mode == FINISH_RYSER_SQ) {
+        per = (f.n & 1) ? -(i128)E : (i128)E;
+      } else {
+        per = (i128)E;
+      }
+      if (f.ot == PERM_OUT_I64) {
+        ((int64_t *)out)[0] = (int64_t)per;
+      } else {
+        ((uint64_t *)out)[0] = (uint64_t)(u128)per;
+        ((uint64_t *)out)[1] = (uint64_t)((u128)per >> 64);
+      }
+    }
+    return;
+  }
+  const int C = kind == ENGINE_CPLX ? 2 : 1;
+  const double *p = (const double *)partials;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  for (int i = t; i < count; i += kReduceThreads) {
+    dd_add(a, b, p[2 * C * i], p[2 * C * i + 1]);
+    if (C == 2) dd_add(c, d, p[4 * i + 2], p[4 * i + 3]);
+  }
+  sh[t][0] = a; sh[t][1] = b; sh[t][2] = c; sh[t][3] = d;
+  __syncthreads();
+  for (int off = kReduceThreads / 2; off > 0; off >>= 1) {
+    if (t < off) {
+      dd_add(sh[t][0], sh[t][1], sh[t + off][0], sh[t + off][1]);
+      dd_add(sh[t][2], sh[t][3], sh[t + off][2], sh[t + off][3]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    double rh = sh[0][0], rl = sh[0][1], ih = sh[0][2], il = sh[0][3];
+    if (f.mode == FINISH_GLYNN) {
+      const double sc = __builtin_ldexp(1.0, -(f.n - 1));
+      rh *= sc; rl *= sc; ih *= sc; il *= sc;            // exact
+      for (int q = 2; q <= f.n - f.m; ++q) {
+        dd_div_d(rh, rl, (double)q);
+        if (C == 2) dd_div_d(ih, il, (double)q);
+      }
+    } else if (f.mode == FINISH_RYSER_SQ && (f.n & 1)) {
+      rh = -rh; rl = -rl; ih = -ih; il = -il;
+    }
+    if (C == 1) {
+      write_real(f.ot, rh, rl, out);
+    } else {
+      double h1, l1, h2, l2;
+      fast_two_sum(rh, rl, h1, l1);
+      fast_two_sum(ih, il, h2, l2);
+      double *o = (double *)out;
+      if (f.ot == PERM_OUT_CDD) {
+        o[0] = h1; o[1] = l1; o[2] = h2; o[3] = l2;
+      } else {
+        o[0] = h1; o[1] = h2;
+      }
+    }
+  }
+}
+
+// Per-line magnitudes of an integer matrix.  mode 0: absolute sum of each
+// logical row, 1: of each column (exact in 64 bits, saturating); mode 2 / 3:
+// sum of squares of each row / column as a double (bit pattern in the slot).
+__global__ void abs_sums_kernel(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                                int mode, uint64_t *sums) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool by_cols = mode == 1 || mode == 3;
+  const int count = by_cols ? n : m;
+  if (idx >= count) return;
+  const int len = by_cols ? m : n;
+  u128 s = 0;
+  double q = 0.0;
+  for (int k = 0; k < len; ++k) {
+    const int i = by_cols ? k : idx, j = by_cols ? idx : k;
+    const int64_t o = tr ? (int64_t)j * lda + i : (int64_t)i * lda + j;
+    int64_t x;
+    if (dt == PERM_I64) x = ((const int64_t *)dA)[o];
+    else x = ((const uint8_t *)dA)[o] ? 1 : 0;
+    s += x < 0 ? (u128)(-(i128)x) : (u128)x;
+    const double xd = (double)x;
+    q = __builtin_fma(xd, xd, q);
+  }
+  if (mode >= 2) sums[idx] = (uint64_t)__double_as_longlong(q);
+  else sums[idx] = (s >> 64) ? ~0ull : (uint64_t)s;
+}
+
+__global__ void write_one_kernel(perm_out ot, void *out) {
+  switch (ot) {
+    case PERM_OUT_F64: ((double *)out)[0] = 1.0; break;
+    case PERM_OUT_DD: ((double *)out)[0] = 1.0; ((double *)out)[1] = 0.0; break;
+    case PERM_OUT_C128: ((double *)out)[0] = 1.0; ((double *)out)[1] = 0.0; break;
+    case PERM_OUT_CDD:
+      ((double *)out)[0] = 1.0;
+      ((double *)out)[1] = ((double *)out)[2] = ((double *)out)[3] = 0.0;
+      break;
+    case PERM_OUT_I64: ((int64_t *)out)[0] = 1; break;
+    default: ((uint64_t *)out)[0] = 1; ((uint64_t *)out)[1] = 0; break;
+  }
+}
+
+// D[(out * l + in)] = col[in] - col[out] over the low columns
+__global__ void stage_rect_kernel(int m, int n, int l, perm_dtype dt, const void *dA, int64_t lda,
+                                  int tr, double *colT, double *D, int C) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  auto rd = [&](int i, int j, double &re, double &im) {
+    const int64_t o = tr ? (int64_t)j * lda + i : (int64_t)i * lda + j;
+    im = 0.0;
+    switch (dt) {
+      case PERM_F64: re = ((const double *)dA)[o]; break;
+      case PERM_C128:
+        re = ((const double *)dA)[2 * o];
+        im = ((const double *)dA)[2 * o + 1];
+        break;
+      case PERM_I64: re = (double)((const int64_t *)dA)[o]; break;
+      default: re = ((const uint8_t *)dA)[o] ? 1.0 : 0.0; break;
+    }
+  };
+  if (idx < n * m) {
+    const int j = idx / m, i = idx % m;
+    double re, im;
+    rd(i, j, re, im);
+    colT[((size_t)j * m + i) * C] = re;
+    if (C == 2) colT[((size_t)j * m + i) * C + 1] = im;
+  }
+  if (idx < l * l * m) {
+    const int pair = idx / m, i = idx % m;
+    const int out = pair / l, in = pair % l;
+    double ro, io, rn, in_;
+    rd(i, out, ro, io);
+    rd(i, in, rn, in_);
+    D[((size_t)pair * m + i) * C] = rn - ro;
+    if (C == 2) D[((size_t)pair * m + i) * C + 1] = in_ - io;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
+                             int tr, double *tbl, double *base, int cplx, hipStream_t s) {
+  const int nv = algo == 0 ? n : m;
+  const int nbits = algo == 0 ? n - 1 : n;
+  int work = nbits * nv > nv ? nbits * nv : nv;
+  if (work < 1) work = 1;
+  const int threads = 256, blocks = (work + threads - 1) / threads;
+  hipLaunchKernelGGL(stage_gray_kernel, dim3(blocks), dim3(threads), 0, s, algo, m, n, dt, dA, lda,
+                     tr, tbl, base, cplx ? 2 : 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(int kind, const void *partials, int count, const Finish &f, void *dOut,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kReduceThreads), 0, s, kind, partials, count, f,
+                     dOut);
+  return hipGetLastError();
+}
+
+hipError_t launch_abs_sums(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                           int by_cols, uint64_t *dSums, hipStream_t s) {
+  const int count = (by_cols == 1 || by_cols == 3) ? n : m;
+  hipLaunchKernelGGL(abs_sums_kernel, dim3((count + 63) / 64), dim3(64), 0, s, m, n, dt, dA, lda,
+                     tr, by_cols, dSums);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_rect(int m, int n, int l, perm_dtype dt, const void *dA, int64_t lda,
+                             int tr, double *colT, double *D, int cplx, hipStream_t s) {
+  int work = n * m > l * l * m ? n * m : l * l * m;
+  if (work < 1) work = 1;
+  hipLaunchKernelGGL(stage_rect_kernel, dim3((work + 255) / 256), dim3(256), 0, s, m, n, l, dt, dA,
+                     lda, tr, colT, D, cplx ? 2 : 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_ryser_rect(int kind, const RectWalk &w, int grid, void *partials,
+                             hipStream_t s) {
+  switch (kind) {
+    case ENGINE_REAL: return launch_ryser_rect_real(w, grid, partials, s);
+    case ENGINE_CPLX: return launch_ryser_rect_cplx(w, grid, partials, s);
+    default: return launch_ryser_rect_int(w, grid, partials, s);
+  }
+}
+
+hipError_t launch_write_one(perm_out ot, void *dOut, hipStream_t s) {
+  hipLaunchKernelGGL(write_one_kernel, dim3(1), dim3(1), 0, s, ot, dOut);
+  return hipGetLastError();
+}
+
+}  // namespace permgpu

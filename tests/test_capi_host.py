@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports
+every function that include/perm.h declares, and answers the calls that do
+not touch a device (version, status strings, algorithm selection)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "perm.h")
+LIB = os.path.join(ROOT, "paper_2510_03421_amd", "libpermgpu.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(perm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libpermgpu.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ["perm_glynn", "perm_ryser", "perm_combinatoric", "perm_auto",
+              "perm_batch_plan_create", "perm_batch_plan_run", "perm_batch_plan_destroy",
+              "perm_glynn_batched", "perm_selector_load", "perm_select", "perm_version",
+              "perm_status_string"]:
+        assert f in names, f
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    for f in declared_functions():
+        getattr(lib, f)
+
+
+def test_version_and_status_strings(lib):
+    lib.perm_version.restype = ctypes.c_int
+    assert lib.perm_version() == 10000
+    lib.perm_status_string.restype = ctypes.c_char_p
+    lib.perm_status_string.argtypes = [ctypes.c_int]
+    seen = set()
+    for s in (0, -1, -2, -3, -4, -5):
+        msg = lib.perm_status_string(s).decode()
+        assert msg and msg not in seen
+        seen.add(msg)
+    assert lib.perm_status_string(-99).decode() == "unknown status"
+
+
+def test_select_is_host_only_and_follows_the_table(lib):
+    chosen, src = ctypes.c_int(-1), ctypes.c_int(-1)
+    lib.perm_select.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.perm_selector_load.argtypes = [ctypes.c_char_p]
+    assert lib.perm_selector_load(None) == 0
+    picks = {}
+    for (m, n) in [(3, 3), (12, 12), (32, 32), (16, 48), (20, 40), (30, 30)]:
+        assert lib.perm_select(m, n, 0, -1.0, ctypes.byref(chosen), ctypes.byref(src)) == 0
+        assert src.value == 0          # no network loaded: the table decides
+        picks[(m, n)] = chosen.value
+    assert picks[(32, 32)] == 2        # Glynn for large square
+    assert picks[(16, 48)] == 1        # Ryser for very rectangular
+    assert picks[(3, 3)] == 0          # the definition for tiny matrices
+    assert lib.perm_select(-1, 3, 0, -1.0, None, None) == -1
+    # the transpose has the same choice
+    assert lib.perm_select(48, 16, 0, -1.0, ctypes.byref(chosen), None) == 0
+    assert chosen.value == picks[(16, 48)]
+
+
+def test_selector_file_errors(lib, tmp_path):
+    lib.perm_selector_load.argtypes = [ctypes.c_char_p]
+    assert lib.perm_selector_load(str(tmp_path / "missing.txt").encode()) == -1
+    bad = tmp_path / "bad.txt"
+    bad.write_text("not-a-selector 1\n")
+    assert lib.perm_selector_load(str(bad).encode()) == -1
+    assert lib.perm_selector_load(None) == 0
