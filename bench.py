@@ -50,13 +50,146 @@ def cpu_baseline(a, budget_s: float = 15.0):
                       f"(double-double Glynn evaluator, {dt:.1f} s)"}
 
 
+def _terms(algo, m, n):
+    from math import comb
+    m, n = min(m, n), max(m, n)
+    if algo == "glynn":
+        return 2 ** (n - 1)
+    if algo == "ryser":
+        return 2 ** n if m == n else sum(comb(n, s) for s in range(1, m + 1))
+    from math import perm
+    return perm(n, m)
+
+
+def suite(args):
+    """Kernel time and Gray-code terms/s of every workload configuration."""
+    import numpy as np
+    import torch
+
+    import paper_2510_03421_amd as pg
+    import workloads
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "reference_values.json")))
+    runs = [("u12", "glynn", None), ("u12", "ryser", None), ("u12", "combinatoric", None),
+            ("u32", "glynn", None), ("u32", "ryser", None), ("c32", "glynn", None),
+            ("b28", "ryser", "i128"), ("b28", "glynn", "i128"), ("b30", "ryser", "i128"),
+            ("u20x40", "ryser", None), ("u20x40", "glynn", None),
+            ("b16x48", "ryser", "i128"), ("u36", "glynn", "dd")]
+    fn = {"glynn": pg.glynn, "ryser": pg.ryser, "combinatoric": pg.combinatoric}
+    pg.profile_enable(True)
+    for name, algo, out in runs:
+        a = torch.from_numpy(workloads.config_matrix(name)).cuda()
+        m, n = a.shape
+        terms = _terms(algo, m, n)
+        r = fn[algo](a, out=out)
+        torch.cuda.synchronize()
+        reps = 1 if terms > 2 ** 38 else max(1, min(args.steps, int(2e10 // max(terms, 1)) + 1))
+        kms, walls = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn[algo](a, out=out)
+            kms.append(pg.profile_last_ms())
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) * 1e3)
+        v = r.value()
+        val = v[0] + v[1] if isinstance(v, tuple) else v
+        rec = gold.get(name)
+        err = None
+        if rec is not None:
+            ref = rec["value"]
+            if isinstance(ref, str):
+                err = 0 if int(ref) == val else abs(int(ref) - val)
+            elif "hi" in ref:
+                err = abs(val - (ref["hi"] + ref["lo"])) / abs(ref["hi"] + ref["lo"])
+            else:
+                refc = complex(ref["re"]["hi"] + ref["re"]["lo"], ref["im"]["hi"] + ref["im"]["lo"])
+                err = abs(complex(val) - refc) / abs(refc)
+        km = float(np.median(kms))
+        print(json.dumps({"workload": name, "m": m, "n": n, "algorithm": algo,
+                          "output": out or "default", "terms": terms, "reps": reps,
+                          "kernel_ms": km, "wall_ms": float(np.median(walls)),
+                          "terms_per_s": terms / (km * 1e-3),
+                          "rel_err_vs_oracle" if not isinstance(err, int) else "int_abs_diff": err}),
+              flush=True)
+    pg.profile_enable(False)
+    batched(args)
+
+
+def batched(args, count: int = 200_000, sample: int = 20_000):
+    """200,000 complex128 submatrices (orders uniform in 4..20) of one seeded
+    64 x 64 Haar unitary: one plan, one graph launch, against a loop of
+    single-matrix launches over the first `sample` matrices."""
+    import numpy as np
+    import torch
+
+    import paper_2510_03421_amd as pg
+    import workloads
+    from paper_2510_03421_amd import _capi as C
+    b = workloads.boson_batch(count, 4, 20, N=64, seed_u=6400, seed_idx=6401)
+    data = torch.from_numpy(b.data).cuda()
+    plan = pg.BatchPlan(b.m, b.n, b.offset, b.ld, data.dtype, out="c128")
+    out = plan.new_output()
+    plan.run(data, out)          # capture
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run(data, out)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    terms = float(np.sum(2.0 ** (b.n.astype(np.float64) - 1)))
+    # per-matrix launches over a sample (same stream, same output type)
+    single = torch.empty(2 * sample, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    dptr = data.data_ptr()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(sample):
+        n = int(b.n[i])
+        C.check(C.lib.perm_glynn(n, n, C.PERM_C128, dptr + 16 * int(b.offset[i]), n,
+                                 C.PERM_OUT_C128, single.data_ptr() + 16 * i, 0, stream),
+                "perm_glynn")
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / sample
+    vb = out[:2 * sample].view(-1, 2)
+    vs = single.view(-1, 2)
+    maxdiff = float((vb - vs).abs().max())
+    bound = float(torch.sqrt((out.view(-1, 2) ** 2).sum(1)).max())
+    print(json.dumps({"workload": "batched_boson_200000_c128_n4..20", "count": count,
+                      "terms": terms, "graph_ms": t_batch * 1e3,
+                      "perms_per_s": count / t_batch, "terms_per_s": terms / t_batch,
+                      "single_launch_perms_per_s": 1.0 / t_single,
+                      "speedup_vs_single_launches": t_single * count / t_batch,
+                      "max_abs_diff_vs_single_on_sample": maxdiff,
+                      "max_abs_per": bound}), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--suite", action="store_true",
+                    help="instead of the one contract line, time every workload "
+                         "configuration (one JSON line each)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="instead of the benchmark, copy a 1 GiB device buffer --steps "
+                         "times (a kernel of known HBM traffic for counter scaling)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": src.numel() * 8,
+                          "copies": max(1, args.steps)}))
+        return
+    if args.suite:
+        suite(args)
+        return
     if args.gpus != 1:
         print("bench.py: this library computes one permanent per GPU call and is "
               "measured on a single GPU; --gpus must be 1", file=sys.stderr)

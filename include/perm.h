@@ -155,28 +155,40 @@ int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out
 /* Batched permanents                                                      */
 /* ---------------------------------------------------------------------- */
 /* A batch is `count` matrices inside one device buffer dData: matrix b is
- * hM[b] x hN[b], row-major with leading dimension hLd[b] (elements), starting
- * at element offset hOffset[b].  The shape arrays are HOST pointers, read
- * during the call only.  dOut receives count values of the output type,
- * contiguous.  One persistent launch serves the whole batch. */
+ * hM[b] x hN[b] with hM[b] <= hN[b] <= 32, row-major with leading dimension
+ * hLd[b] >= hN[b] (elements), starting at element offset hOffset[b].  The
+ * shape arrays are HOST pointers, read during the call only.  dOut receives
+ * `count` values of the output type, contiguous.  Supported: Glynn's formula
+ * (square, and rectangular by padding with rows of ones) for PERM_F64 and
+ * PERM_C128 input.  A matrix with hM[b] = 0 has permanent 1.
+ *
+ * The Gray-code terms of each matrix are cut into chunks (work items); one
+ * persistent kernel per matrix order serves all items of that order, every
+ * item writes its own partial slot, and one finishing kernel adds each
+ * matrix's slots in a fixed order -- results are bitwise reproducible. */
 typedef struct perm_batch_plan perm_batch_plan;
 
-/* Build a plan (work list, scratch buffers) for a batch of shapes and an
- * algorithm (PERM_ALGO_GLYNN, or PERM_ALGO_RYSER for square shapes).  The plan
- * is bound to the current device.  *plan receives an owning handle. */
+/* Build a plan (descriptors, work list, scratch) for a batch of shapes.
+ * algo must be PERM_ALGO_GLYNN (PERM_E_UNSUPPORTED otherwise, and for integer
+ * input/output or hM[b] > hN[b]); hN[b] > 32 gives PERM_E_TOO_LARGE.  The plan
+ * is bound to the current device and owns its device memory.  Synchronous. */
 int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
                            const int64_t *hOffset, const int64_t *hLd, perm_dtype dt,
                            perm_out ot, perm_algo algo, uint32_t flags, perm_batch_plan **plan);
 
-/* Run a plan on (dData, dOut).  The first run for a given (dData, dOut,
- * stream) captures the launch sequence into a hipGraph owned by the plan;
- * later runs with the same pointers replay it. */
+/* Run a plan on (dData, dOut), asynchronously on `stream`.  The first run for
+ * a (dData, dOut) pair captures the launch sequence (counter reset, the
+ * per-order kernels, the finishing kernel) into a hipGraph owned by the plan;
+ * later runs with the same pointers replay it with one graph launch.  Runs of
+ * one plan must not overlap (they share the plan's scratch). */
 int perm_batch_plan_run(perm_batch_plan *plan, const void *dData, void *dOut, void *stream);
 
-/* Release the plan and its graph and scratch memory (NULL is ignored). */
+/* Release the plan, its graph and its device memory (NULL is ignored).  The
+ * caller must make sure no run of the plan is still executing. */
 int perm_batch_plan_destroy(perm_batch_plan *plan);
 
-/* One-shot convenience: create, run (without graph capture), destroy. */
+/* One-shot convenience: create a plan, launch it without graph capture, wait
+ * for the stream, destroy the plan. */
 int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
                        const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
                        void *dOut, uint32_t flags, void *stream);

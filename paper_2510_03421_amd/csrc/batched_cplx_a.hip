@@ -1,0 +1,8 @@
+// Batched Glynn instantiations: cplx kind, matrix orders 1..20.
+#include "internal.h"
+#define BATCH_KIND ENGINE_CPLX
+#define BATCH_NV_LO 1
+#define BATCH_NV_HI 20
+#define BATCH_LAUNCH_NAME batched_launch_cplx_a
+#define BATCH_OCC_NAME batched_occ_cplx_a
+#include "batched.inc"

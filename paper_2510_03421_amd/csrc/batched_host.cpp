@@ -1,35 +1,243 @@
-// C ABI of the batched path (plan, run, destroy).
+// C ABI of the batched path: planning (descriptors, work items grouped by
+// matrix order, scratch), graph capture and replay.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
 #include "runtime.h"
+
+using namespace permgpu;
+
+struct perm_batch_plan {
+  int dev = 0;
+  int count = 0;
+  int kind = ENGINE_REAL;
+  perm_out ot = PERM_OUT_F64;
+  std::vector<BatchBucket> buckets;
+  BatchMatrix *d_mats = nullptr;
+  uint32_t *d_item_matrix = nullptr;
+  uint32_t *d_item_chunk = nullptr;
+  double *d_slots = nullptr;
+  double *d_ones = nullptr;
+  // the captured launch sequence for one (data, out) pair
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void *g_data = nullptr;
+  void *g_out = nullptr;
+};
+
+namespace {
+
+void release(perm_batch_plan *p) {
+  if (!p) return;
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->capture_stream) hipStreamDestroy(p->capture_stream);
+  hipFree(p->d_mats);
+  hipFree(p->d_item_matrix);
+  hipFree(p->d_item_chunk);
+  hipFree(p->d_slots);
+  hipFree(p->d_ones);
+  delete p;
+}
+
+// log2 of the lane-block length for a matrix with 2^nbits terms: long blocks
+// (fewer closed-form seeds) but at least 128 blocks (one wave's two passes)
+// when the matrix is large enough.
+int batch_block_log2(int nbits) {
+  static const int cap = [] {
+    const char *e = std::getenv("PERM_BATCH_BLOCK_LOG2");
+    const int v = e ? std::atoi(e) : 9;
+    return v >= 0 && v <= 16 ? v : 9;
+  }();
+  int b = nbits - 7;  // 2^7 = 128 blocks per chunk
+  return std::max(0, std::min(b, cap));
+}
+
+BatchLaunch make_launch(const perm_batch_plan *p, const void *data, void *out) {
+  BatchLaunch L;
+  L.kind = p->kind;
+  L.mats = p->d_mats;
+  L.count = p->count;
+  L.item_matrix = p->d_item_matrix;
+  L.item_chunk = p->d_item_chunk;
+  L.data = data;
+  L.ones = p->d_ones;
+  L.slots = p->d_slots;
+  L.buckets = p->buckets.data();
+  L.nbuckets = (int)p->buckets.size();
+  L.ot = p->ot;
+  L.out = out;
+  return L;
+}
+
+template <class T>
+int upload(T **dst, const std::vector<T> &src) {
+  const size_t bytes = sizeof(T) * std::max<size_t>(1, src.size());
+  if (hipMalloc((void **)dst, bytes) != hipSuccess) return PERM_E_HIP;
+  if (!src.empty() &&
+      hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return PERM_E_HIP;
+  return PERM_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
                            const int64_t *hOffset, const int64_t *hLd, perm_dtype dt,
                            perm_out ot, perm_algo algo, uint32_t flags, perm_batch_plan **plan) {
-  (void)count; (void)hM; (void)hN; (void)hOffset; (void)hLd; (void)dt; (void)ot; (void)algo;
   (void)flags;
-  if (plan) *plan = nullptr;
-  return PERM_E_UNSUPPORTED;
+  if (!plan) return PERM_E_INVALID;
+  *plan = nullptr;
+  if (count < 0 || (count > 0 && (!hM || !hN || !hOffset || !hLd))) return PERM_E_INVALID;
+  int kind = 0;
+  int rc = engine_kind_for(dt, ot, kind);
+  if (rc) return rc;
+  if (algo != PERM_ALGO_GLYNN) return PERM_E_UNSUPPORTED;
+  if (kind == ENGINE_INT) return PERM_E_UNSUPPORTED;
+  for (int i = 0; i < count; ++i) {
+    if (hM[i] < 0 || hN[i] < 0 || hOffset[i] < 0) return PERM_E_INVALID;
+    if (hM[i] > 0 && hLd[i] < hN[i]) return PERM_E_INVALID;
+    if (hM[i] > hN[i]) return PERM_E_UNSUPPORTED;
+    if (hN[i] > BATCH_MAX_N) return PERM_E_TOO_LARGE;
+  }
+  perm_batch_plan *p = new perm_batch_plan();
+  if (hipGetDevice(&p->dev) != hipSuccess) {
+    delete p;
+    return PERM_E_HIP;
+  }
+  p->count = count;
+  p->kind = kind;
+  p->ot = ot;
+  // descriptors and slots
+  std::vector<BatchMatrix> mats(count);
+  uint64_t slot = 0;
+  std::vector<std::vector<uint32_t>> by_n(BATCH_MAX_N + 1);
+  for (int i = 0; i < count; ++i) {
+    BatchMatrix &d = mats[i];
+    std::memset(&d, 0, sizeof d);
+    d.offset = hOffset[i];
+    d.ld = hLd[i];
+    d.m = hM[i];
+    d.n = hM[i] == 0 ? 0 : hN[i];  // an empty product (m = 0) has per = 1
+    d.first_slot = (uint32_t)slot;
+    if (d.n > 0) {
+      const int nbits = d.n - 1;
+      d.b = batch_block_log2(nbits);
+      const uint64_t nblocks = 1ull << (nbits - d.b);
+      d.nchunks = (uint32_t)((nblocks + 127) / 128);
+      slot += d.nchunks;
+      by_n[d.n].push_back((uint32_t)i);
+    }
+  }
+  if (slot >= (1ull << 32)) {
+    delete p;
+    return PERM_E_TOO_LARGE;
+  }
+  // work items grouped by order, one bucket (one persistent kernel) per order
+  std::vector<uint32_t> item_matrix, item_chunk;
+  const int cus = device_cus();
+  for (int n = BATCH_MAX_N; n >= 1; --n) {
+    if (by_n[n].empty()) continue;
+    BatchBucket bk;
+    bk.n = n;
+    bk.item_begin = (uint32_t)item_matrix.size();
+    for (uint32_t i : by_n[n])
+      for (uint32_t c = 0; c < mats[i].nchunks; ++c) {
+        item_matrix.push_back(i);
+        item_chunk.push_back(c);
+      }
+    bk.item_end = (uint32_t)item_matrix.size();
+    const int bpc = std::max(1, batched_blocks_per_cu(kind, n));
+    const uint64_t waves_needed = bk.item_end - bk.item_begin;
+    const uint64_t groups = std::min<uint64_t>((uint64_t)cus * bpc, (waves_needed + 3) / 4);
+    bk.grid = (int)std::max<uint64_t>(1, groups);
+    p->buckets.push_back(bk);
+  }
+  std::vector<double> ones(2 * BATCH_MAX_N);
+  for (int j = 0; j < BATCH_MAX_N; ++j) {
+    const int C = kind == ENGINE_CPLX ? 2 : 1;
+    ones[C * j] = 1.0;
+    if (C == 2) ones[2 * j + 1] = 0.0;
+  }
+  const size_t C = kind == ENGINE_CPLX ? 2 : 1;
+  if ((rc = upload(&p->d_mats, mats)) || (rc = upload(&p->d_item_matrix, item_matrix)) ||
+      (rc = upload(&p->d_item_chunk, item_chunk)) || (rc = upload(&p->d_ones, ones))) {
+    release(p);
+    return rc;
+  }
+  if (hipMalloc((void **)&p->d_slots, sizeof(double) * 2 * C * std::max<uint64_t>(1, slot)) !=
+          hipSuccess ||
+      hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    release(p);
+    return PERM_E_HIP;
+  }
+  *plan = p;
+  return PERM_OK;
 }
 
-int perm_batch_plan_run(perm_batch_plan *plan, const void *dData, void *dOut, void *stream) {
-  (void)plan; (void)dData; (void)dOut; (void)stream;
-  return PERM_E_UNSUPPORTED;
+int perm_batch_plan_run(perm_batch_plan *p, const void *dData, void *dOut, void *stream) {
+  if (!p || (p->count > 0 && (!dData || !dOut))) return PERM_E_INVALID;
+  if (p->count == 0) return PERM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->dev) return PERM_E_INVALID;
+  if (!p->exec || p->g_data != dData || p->g_out != dOut) {
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    // capture on the plan's own stream, so that any caller stream (including
+    // the default one) can launch the graph
+    const BatchLaunch L = make_launch(p, dData, dOut);
+    if (hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return PERM_E_HIP;
+    hipError_t e = launch_batched(L, p->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p->capture_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return PERM_E_HIP;
+    }
+    if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(g);
+      return PERM_E_HIP;
+    }
+    p->graph = g;
+    p->g_data = dData;
+    p->g_out = dOut;
+  }
+  return hipGraphLaunch(p->exec, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
 }
 
-int perm_batch_plan_destroy(perm_batch_plan *plan) {
-  (void)plan;
+int perm_batch_plan_destroy(perm_batch_plan *p) {
+  release(p);
   return PERM_OK;
 }
 
 int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
                        const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
                        void *dOut, uint32_t flags, void *stream) {
-  (void)count; (void)hM; (void)hN; (void)hOffset; (void)hLd; (void)dt; (void)dData; (void)ot;
-  (void)dOut; (void)flags; (void)stream;
-  return PERM_E_UNSUPPORTED;
+  if (count > 0 && (!dOut || !dData)) return PERM_E_INVALID;
+  perm_batch_plan *p = nullptr;
+  int rc = perm_batch_plan_create(count, hM, hN, hOffset, hLd, dt, ot, PERM_ALGO_GLYNN, flags, &p);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (count == 0) {
+    release(p);
+    return PERM_OK;
+  }
+  hipError_t e = launch_batched(make_launch(p, dData, dOut), s);
+  // the plan's buffers are released only after the work using them is done
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release(p);
+  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
 }
 
 }  // extern "C"

@@ -1,0 +1,8 @@
+// Batched Glynn instantiations: real kind, matrix orders 21..32.
+#include "internal.h"
+#define BATCH_KIND ENGINE_REAL
+#define BATCH_NV_LO 21
+#define BATCH_NV_HI 32
+#define BATCH_LAUNCH_NAME batched_launch_real_b
+#define BATCH_OCC_NAME batched_occ_real_b
+#include "batched.inc"

@@ -94,10 +94,10 @@ int plan_gray(int kind, int nv, int nbits, GrayPlan &p) {
   if (nbits == 0) {
     b = 0;
   } else {
-    // enough blocks per lane to amortise the tail, blocks of at most 2^10
-    // steps between closed-form re-seeds
-    b = nbits - lg - 4;
-    b = std::max(1, std::min(b, 10));
+    // as long as possible (up to 2^12 steps between closed-form re-seeds)
+    // while every lane still gets at least two blocks
+    b = nbits - lg - 1;
+    b = std::max(1, std::min(b, 12));
     const int bo = env_int("PERM_BLOCK_LOG2", -1);
     if (bo >= 1) b = bo;
     b = std::min(b, nbits);

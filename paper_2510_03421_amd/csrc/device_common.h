@@ -64,6 +64,50 @@ __device__ __forceinline__ double prod_range(const T &v) {
   }
 }
 
+// product of v[0..NV) as K interleaved left-to-right chains combined at the
+// end: fewer live temporaries than the balanced tree (K instead of NV/2)
+template <int NV, int K, class T>
+__device__ __forceinline__ double prod_chains(const T &v) {
+  if constexpr (NV < 2 * K) {
+    return prod_range<0, NV>(v);
+  } else {
+    double c[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = v[k];
+#pragma unroll
+    for (int j = K; j < NV; ++j) c[j % K] *= v[j];
+    return prod_range<0, K>(c);
+  }
+}
+
+// The same products split into two final factors (x, y) with x*y the full
+// product, so that an accumulation s +- x*y can be one FMA.
+template <int NV, class T>
+__device__ __forceinline__ void prod_split_tree(const T &v, double &x, double &y) {
+  if constexpr (NV == 1) {
+    x = v[0];
+    y = 1.0;
+  } else {
+    constexpr int M = NV / 2;
+    x = prod_range<0, M>(v);
+    y = prod_range<M, NV>(v);
+  }
+}
+template <int NV, int K, class T>
+__device__ __forceinline__ void prod_split_chains(const T &v, double &x, double &y) {
+  if constexpr (NV < 2 * K || K < 2) {
+    prod_split_tree<NV>(v, x, y);
+  } else {
+    double c[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = v[k];
+#pragma unroll
+    for (int j = K; j < NV; ++j) c[j % K] *= v[j];
+    x = prod_range<0, K / 2>(c);
+    y = prod_range<K / 2, K>(c);
+  }
+}
+
 // complex product over (vr, vi) with explicit FMA:
 //   (a + ib)(c + id) = (ac - bd) + i(ad + bc)
 __device__ __forceinline__ void cmul(double ar, double ai, double br, double bi, double &cr,
@@ -84,6 +128,30 @@ __device__ __forceinline__ void cprod_range(const T &vr, const T &vi, double &pr
     cprod_range<L, M>(vr, vi, ar, ai);
     cprod_range<M, R>(vr, vi, br, bi);
     cmul(ar, ai, br, bi, pr, pi);
+  }
+}
+
+// complex product as K interleaved chains of complex multiplies, combined by
+// a balanced tree at the end
+template <int NV, int K, class T>
+__device__ __forceinline__ void cprod_chains(const T &vr, const T &vi, double &pr, double &pi) {
+  if constexpr (NV < 2 * K) {
+    cprod_range<0, NV>(vr, vi, pr, pi);
+  } else {
+    double cr[K], ci[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      cr[k] = vr[k];
+      ci[k] = vi[k];
+    }
+#pragma unroll
+    for (int j = K; j < NV; ++j) {
+      double r, i;
+      cmul(cr[j % K], ci[j % K], vr[j], vi[j], r, i);
+      cr[j % K] = r;
+      ci[j % K] = i;
+    }
+    cprod_range<0, K>(cr, ci, pr, pi);
   }
 }
 

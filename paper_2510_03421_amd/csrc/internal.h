@@ -18,6 +18,7 @@ constexpr int kMaxN = 64;        // largest side accepted by any path
 #ifndef RECT_MAX_M
 #define RECT_MAX_M 40
 #endif
+#define BATCH_MAX_N 32
 constexpr int kReduceThreads = 256;
 
 // Element kind of the Gray-code engine.
@@ -61,6 +62,43 @@ struct RectWalk {
   int a_lo, a_hi;
   int prod_levels;
   uint64_t total_cost;
+};
+
+// Batched Glynn: one descriptor per matrix (m <= n, row-major, ld elements),
+// b = log2 of the lane block, nchunks chunks of 128 blocks, partial slots
+// first_slot .. first_slot + nchunks - 1.
+struct BatchMatrix {
+  int64_t offset;
+  int64_t ld;
+  int32_t m, n;
+  int32_t b;
+  uint32_t nchunks;
+  uint32_t first_slot;
+  uint32_t pad_;
+};
+
+// The work items of all matrices of one order n: items [item_begin, item_end)
+// of the item list, served round-robin by a persistent kernel of `grid`
+// workgroups.
+struct BatchBucket {
+  int n;
+  uint32_t item_begin, item_end;
+  int grid;
+};
+
+struct BatchLaunch {
+  int kind;  // ENGINE_REAL or ENGINE_CPLX
+  const BatchMatrix *mats;
+  int count;
+  const uint32_t *item_matrix;  // work items grouped by order n
+  const uint32_t *item_chunk;
+  const void *data;
+  const double *ones;  // BATCH_MAX_N entries of 1 (complex: (1, 0) pairs)
+  double *slots;
+  const BatchBucket *buckets;  // host array
+  int nbuckets;
+  perm_out ot;
+  void *out;
 };
 
 struct Finish {
@@ -113,6 +151,10 @@ hipError_t launch_ryser_rect_int(const RectWalk &w, int grid, void *partials, hi
 // partial per workgroup.
 hipError_t launch_combinatoric(int kind, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
                                int tr, uint64_t total, int grid, void *partials, hipStream_t s);
+
+// Batched Glynn: the per-order persistent kernels and the per-matrix finish.
+hipError_t launch_batched(const BatchLaunch &L, hipStream_t s);
+int batched_blocks_per_cu(int kind, int n);  // resident 256-thread workgroups per CU
 
 // Writes the value 1 in the output type (the permanent of an empty matrix).
 hipError_t launch_write_one(perm_out ot, void *dOut, hipStream_t s);

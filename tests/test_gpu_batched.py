@@ -1,0 +1,145 @@
+"""Batched Glynn (one plan, per-order persistent kernels, one graph launch)
+against the CPU oracle and against the single-matrix path."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def pack(mats, dtype):
+    """Pack a list of 2-D arrays into one buffer (row-major, ld = n)."""
+    m = np.array([a.shape[0] for a in mats], dtype=np.int32)
+    n = np.array([a.shape[1] for a in mats], dtype=np.int32)
+    off = np.zeros(len(mats), dtype=np.int64)
+    tot = 0
+    for i, a in enumerate(mats):
+        off[i] = tot
+        tot += a.size
+    data = np.zeros(max(tot, 1), dtype=dtype)
+    for i, a in enumerate(mats):
+        data[off[i]:off[i] + a.size] = a.reshape(-1)
+    return data, m, n, off, n.astype(np.int64)
+
+
+def to_values(out, kind, count):
+    v = out.cpu().numpy()
+    if kind == "f64":
+        return v
+    if kind == "c128":
+        return v[0::2] + 1j * v[1::2]
+    if kind == "dd":
+        return v[0::2] + v[1::2]
+    return (v[0::4] + v[1::4]) + 1j * (v[2::4] + v[3::4])
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_random_shapes_against_oracle(cplx):
+    import torch
+
+    import paper_2510_03421_amd as pg
+    rng = np.random.default_rng(11 + cplx)
+    mats = []
+    for k in range(60):
+        n = int(rng.integers(1, 10))
+        m = int(rng.integers(0, n + 1)) if k % 3 == 0 else n   # some rectangular, some m = 0
+        mats.append(workloads.complex_gauss(m, n, 500 + k) if cplx else
+                    workloads.uniform(m, n, 500 + k))
+    dt = np.complex128 if cplx else np.float64
+    data, m, n, off, ld = pack(mats, dt)
+    t = torch.from_numpy(data).cuda()
+    plan = pg.BatchPlan(m, n, off, ld, t.dtype, out="cdd" if cplx else "dd")
+    out = plan.new_output()
+    plan.run(t, out)
+    got = to_values(out, plan.kind, len(mats))
+    for i, a in enumerate(mats):
+        ref = complex(oracle.per_brute(a)) if a.shape[0] else 1.0
+        scale = float(oracle.per_brute(np.abs(a))) if a.shape[0] else 1.0
+        # padded rectangular Glynn is ill-conditioned; the bound covers it
+        bound = 1e-11 * scale * (1.0 if a.shape[0] == a.shape[1] else 1e3) + 1e-300
+        assert abs(got[i] - ref) <= max(bound, 64 * a.shape[1] * U * scale), (i, a.shape, got[i], ref)
+    plan.close()
+
+
+def test_graph_replays_are_identical_and_match_single_calls():
+    import torch
+
+    import paper_2510_03421_amd as pg
+    b = workloads.boson_batch(600, 4, 16, N=32, seed_u=77, seed_idx=78)
+    t = torch.from_numpy(b.data).cuda()
+    plan = pg.BatchPlan(b.m, b.n, b.offset, b.ld, t.dtype, out="c128")
+    out = plan.new_output()
+    plan.run(t, out)
+    torch.cuda.synchronize()
+    first = out.clone()
+    for r in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        out.zero_()
+        plan.run(t, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, first), r
+        del junk
+    vals = to_values(first, "c128", b.count)
+    for i in range(0, b.count, 7):
+        single = pg.glynn(torch.from_numpy(np.ascontiguousarray(b.matrix(i))).cuda()).value()
+        assert abs(vals[i] - single) <= 1e-12 * (1 + abs(single))
+        assert abs(vals[i]) <= 1 + 1e-9          # submatrix of a unitary: |per| <= 1
+    plan.close()
+
+
+def test_boson_sample_against_oracle():
+    import torch
+
+    import paper_2510_03421_amd as pg
+    b = workloads.boson_batch(300, 4, 12, N=64, seed_u=6400, seed_idx=6401)
+    t = torch.from_numpy(b.data).cuda()
+    out = pg.glynn_batched(t, b.m, b.n, b.offset, b.ld, out="cdd")
+    vals = to_values(out, "cdd", b.count)
+    for i in range(0, b.count, 3):
+        a = b.matrix(i)
+        ref = complex(oracle.per_laplace(np.ascontiguousarray(a)))
+        scale = float(oracle.per_laplace(np.abs(a)))
+        assert abs(vals[i] - ref) <= 1e-13 * scale + 1e-300, (i, vals[i], ref)
+
+
+def test_large_orders_use_many_chunks():
+    import torch
+
+    import paper_2510_03421_amd as pg
+    mats = [workloads.uniform(n, n, 900 + n) for n in (17, 20, 22, 24)]
+    data, m, n, off, ld = pack(mats, np.float64)
+    t = torch.from_numpy(data).cuda()
+    plan = pg.BatchPlan(m, n, off, ld, t.dtype, out="dd")
+    out = plan.new_output()
+    plan.run(t, out)
+    got = to_values(out, "dd", len(mats))
+    for i, a in enumerate(mats):
+        single = pg.glynn(torch.from_numpy(a).cuda(), out="dd").value()
+        assert abs(got[i] - (single[0] + single[1])) <= 1e-12 * abs(single[0])
+    plan.close()
+
+
+def test_empty_batch_and_errors():
+    import torch
+
+    import paper_2510_03421_amd as pg
+    e = np.zeros(0, dtype=np.int32)
+    plan = pg.BatchPlan(e, e, e.astype(np.int64), e.astype(np.int64), torch.float64)
+    out = plan.new_output()
+    plan.run(torch.zeros(1, dtype=torch.float64, device="cuda"), out)
+    plan.close()
+    one = np.array([3], dtype=np.int32)
+    with pytest.raises(pg.PermError) as ex:        # m > n
+        pg.BatchPlan(np.array([4], np.int32), one, np.zeros(1, np.int64), np.array([4]),
+                     torch.float64)
+    assert ex.value.status == -5
+    with pytest.raises(pg.PermError) as ex:        # n > 32
+        pg.BatchPlan(np.array([33], np.int32), np.array([33], np.int32), np.zeros(1, np.int64),
+                     np.array([33]), torch.float64)
+    assert ex.value.status == -2
+    with pytest.raises(pg.PermError) as ex:        # integer batches are not served
+        pg.BatchPlan(one, one, np.zeros(1, np.int64), np.array([3]), torch.int64)
+    assert ex.value.status == -5
