@@ -29,6 +29,26 @@ OPS_PER_TERM = 2 * N          # N adds (update) + (N-1) multiplies + 1 add (accu
 PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9
 
 
+def profiled_traffic():
+    """HBM bytes per engine launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None if the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "glynn32_f64_engine.txt")
+    if not os.path.exists(path):
+        return None
+    src = os.path.join(ROOT, "paper_2510_03421_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("gray_engine.inc", "device_common.h"):
+        h.update(open(os.path.join(src, f), "rb").read())
+    text = open(path).read()
+    if f"kernel_source_sha256_16: {h.hexdigest()[:16]}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":")[1])
+    return None
+
+
 def cpu_baseline(a, budget_s: float = 15.0):
     """The oracle's double-double Glynn evaluator timed on a bounded sample of
     the same workload: the first K Gray-code terms of the 32 x 32 matrix."""
@@ -264,7 +284,7 @@ def main():
         "config": {"workload": "glynn_32x32_f64_uniform[-1,1]", "m": N, "n": N, "seed": SEED,
                    "terms": TERMS, "algorithm": "glynn", "output": "double-double"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": profiled_traffic(),
                      "kernel_ms": kernel_ms,
                      "note": "FP64 add/mul lane-ops (1 each) of the Gray-walk engine kernel: "
                              "64 per term x 2^31 terms; peak = FP64 VALU issue rate "
