@@ -142,12 +142,16 @@ int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_ou
 int perm_combinatoric(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                       void *dOut, uint32_t flags, void *stream);
 
-/* perm_auto -- picks one of the three algorithms from (m, n, density, dtype)
- * with the learned selector if one is loaded (perm_selector_load), else with
- * the threshold table modelled on the paper's Alg. 5 (App. B), and runs it.
- * The value does not depend on the choice beyond rounding; integer outputs
- * are identical.  *chosen (may be NULL) receives the algorithm used.
- * density < 0 means "unknown" (treated as 1). */
+/* perm_auto -- ranks the algorithms whose size limits admit the shape by
+ * (m, n, density, dtype) with the learned selector if one is loaded
+ * (perm_selector_load), else with the threshold table modelled on the
+ * paper's Alg. 5 (App. B), and runs the first one; if that one refuses the
+ * input with PERM_E_TOO_LARGE or PERM_E_OVERFLOW (e.g. Glynn's integer sum
+ * carries an extra factor 2^(n-1) (n-m)!) the next one is tried.  The value
+ * does not depend on the choice beyond rounding; integer outputs are
+ * identical.  *chosen (may be NULL) receives the algorithm that ran.
+ * density < 0 means "unknown" (treated as 1).  Returns the last refusal if
+ * every algorithm refuses. */
 int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
               void *dOut, uint32_t flags, void *stream, double density, perm_algo *chosen);
 
@@ -196,13 +200,102 @@ int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const in
 /* ---------------------------------------------------------------------- */
 /* Algorithm selection                                                     */
 /* ---------------------------------------------------------------------- */
-/* Load selector weights written by perm_selector_save (text format).  path
- * NULL unloads them (perm_auto then uses the threshold table). */
+/* The three algorithms return the same value (Sec. 1.2); only their cost
+ * differs, and which is fastest depends on the shape (Sec. 3.2 and App. B,
+ * where the paper picks with a threshold table, Alg. 5).  perm_auto ranks the
+ * algorithms whose size limits admit the shape either by a small network's
+ * predicted run time or, when no network is loaded, by a table of Alg. 5's
+ * form, and runs the first one that accepts the input. */
+
+/* Load selector weights (the text format written by perm_selector_save);
+ * path NULL unloads them (perm_auto then uses the threshold table).
+ * PERM_E_INVALID if the file cannot be read or is malformed (the previous
+ * weights stay loaded). */
 int perm_selector_load(const char *path);
 
-/* The choice perm_auto would make, without running anything.  *source (may
- * be NULL) receives 1 if the learned selector decided, 0 for the table. */
+/* The algorithm perm_auto would try first, without running anything, for
+ * the default output type of dt (PERM_I64 / PERM_B8: exact integers).
+ * *source (may be NULL) receives 1 if the network decided, 0 for the table.
+ * PERM_E_TOO_LARGE if no algorithm admits the shape. */
 int perm_select(int m, int n, perm_dtype dt, double density, perm_algo *chosen, int *source);
+
+/* The selector's input features of a problem: x[0] = log min(m,n),
+ * x[1] = log max(m,n), x[2] = density (fraction of nonzero entries; a
+ * negative value means unknown and gives 1), x[3] = 0 for PERM_F64, 1 for
+ * PERM_C128, 2 for PERM_I64 and PERM_B8.  x is a HOST array of 4 floats. */
+int perm_selector_features(int m, int n, perm_dtype dt, double density, float *x);
+
+/* perm_time -- timing of one algorithm, the selector's training data.  Runs
+ * `algo` on the device matrix dA (arguments as for perm_glynn) 1 + reps times
+ * on `stream`, waiting for the stream after each run, and returns in *ms the
+ * median host wall time (call to completion) of the last reps runs.  With
+ * fraction < 1 the algorithm's main kernel does only about that fraction of
+ * its work so that a caller can extrapolate the time of a long run from short
+ * ones: Glynn and square Ryser run fewer Gray-code blocks per lane (never
+ * fewer than two), rectangular Ryser stops every revolving-door walk after a
+ * cap on its transitions (every subset of the lane part is still visited),
+ * the combinatoric sum runs a prefix of the maps.  *fraction_run (may be
+ * NULL) receives the fraction of the work actually run.  The value computed
+ * is discarded.  Errors: those of the algorithm's entry point, and
+ * PERM_E_INVALID for fraction outside (0, 1], reps < 1 or ms NULL.
+ * Synchronous. */
+int perm_time(perm_algo algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
+              perm_out ot, uint32_t flags, double fraction, int reps, void *stream, double *ms,
+              double *fraction_run);
+
+/* ---- the selector network on the GPU (FP32) ----
+ * Network 4 -> 64 -> 64 -> 3 with ReLU hidden layers on normalised features
+ * z = (x - mean) / std, outputs y[k] = predicted log run time of perm_algo k.
+ * Parameters: one DEVICE array of PERM_MLP_PARAMS floats,
+ *   W1[64][4] | b1[64] | W2[64][64] | b2[64] | W3[3][64] | b3[3]
+ * (weights row-major [output][input]); norm: DEVICE float[8] = mean[4] | std[4].
+ * X: DEVICE float[batch][4]; T, Y: DEVICE float[batch][3].  A NaN target
+ * (algorithm not available for that shape) takes no part in the loss
+ *   L = scale * sum over finite T[b][k] of (Y[b][k] - T[b][k])^2.
+ * All three are asynchronous on `stream` and deterministic (fixed-order sums). */
+#define PERM_MLP_PARAMS 4675
+
+/* Y = network(X). */
+int perm_mlp_forward(const float *dParams, const float *dNorm, const float *dX, int batch,
+                     float *dY, void *stream);
+
+/* dGrad (DEVICE float[PERM_MLP_PARAMS]) = dL/dParams, *dLoss (DEVICE float,
+ * may be NULL) = L.  Uses stream-ordered scratch for per-workgroup partials. */
+int perm_mlp_grad(const float *dParams, const float *dNorm, const float *dX, const float *dT,
+                  int batch, float scale, float *dGrad, float *dLoss, void *stream);
+
+/* One Adam step (Kingma & Ba, 2015, with bias correction) on dParams.
+ * dState: DEVICE array of 3 * PERM_MLP_PARAMS 32-bit words, zero before the
+ * first step: first moments (float), second moments (float), and each
+ * parameter's step count (int32).  total_steps > 0 decays the rate as
+ * lr * (1 + cos(pi * min(t, total_steps) / total_steps)) / 2 at step t;
+ * 0 keeps it constant. */
+int perm_mlp_adam(float *dParams, const float *dGrad, float *dState, float lr, float beta1,
+                  float beta2, float eps, int total_steps, void *stream);
+
+/* Full-batch training on the GPU with the kernels above: feature statistics
+ * of hX go to hNorm (HOST float[8]); with init != 0 hParams (HOST
+ * float[PERM_MLP_PARAMS]) is first set from `seed` (He-uniform weights,
+ * zero hidden biases, output biases at the mean finite target), otherwise
+ * training starts from the values it holds.  One epoch (gradient with
+ * scale = 1 / number of finite targets, Adam with beta1 0.9, beta2 0.999,
+ * eps 1e-8 and cosine decay over `epochs`) is captured once in a hipGraph and
+ * replayed `epochs` times.  On return hParams holds the trained parameters and
+ * hLoss (HOST float[epochs], may be NULL) the loss before each step.  hX:
+ * HOST float[count][4] features (perm_selector_features), hT: HOST
+ * float[count][3] log run times.  Synchronous. */
+int perm_selector_train(int count, const float *hX, const float *hT, int epochs, float lr,
+                        uint64_t seed, int init, float *hParams, float *hNorm, float *hLoss,
+                        void *stream);
+
+/* Write a weights file for perm_selector_load: hParams (HOST, as above),
+ * hNorm (HOST float[8]) and, if hTable is not NULL, threshold-table values
+ * p1..p8 (HOST double[8]) in Alg. 5's form: with r = m/n,
+ *   n <= p8: square and n <= p4 -> combinatoric; p1 r + p2 n + p3 > 0 ->
+ *            combinatoric; otherwise Glynn;
+ *   n >  p8: p5 r + p6 n + p7 > 0 -> Glynn, otherwise Ryser. */
+int perm_selector_save(const char *path, const float *hParams, const float *hNorm,
+                       const double *hTable);
 
 #ifdef __cplusplus
 }

@@ -58,6 +58,24 @@ lib.perm_selector_load.argtypes = [ctypes.c_char_p]
 lib.perm_selector_load.restype = _i32
 lib.perm_select.argtypes = [_i32, _i32, _i32, _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
 lib.perm_select.restype = _i32
+lib.perm_selector_features.argtypes = [_i32, _i32, _i32, _d, _p]
+lib.perm_selector_features.restype = _i32
+lib.perm_time.argtypes = [_i32, _i32, _i32, _i32, _p, _i64, _i32, _u32, _d, _i32, _p,
+                          ctypes.POINTER(_d), ctypes.POINTER(_d)]
+lib.perm_time.restype = _i32
+_f = ctypes.c_float
+lib.perm_mlp_forward.argtypes = [_p, _p, _p, _i32, _p, _p]
+lib.perm_mlp_forward.restype = _i32
+lib.perm_mlp_grad.argtypes = [_p, _p, _p, _p, _i32, _f, _p, _p, _p]
+lib.perm_mlp_grad.restype = _i32
+lib.perm_mlp_adam.argtypes = [_p, _p, _p, _f, _f, _f, _f, _i32, _p]
+lib.perm_mlp_adam.restype = _i32
+lib.perm_selector_train.argtypes = [_i32, _p, _p, _i32, _f, ctypes.c_uint64, _i32, _p, _p, _p,
+                                    _p]
+lib.perm_selector_train.restype = _i32
+lib.perm_selector_save.argtypes = [ctypes.c_char_p, _p, _p, _p]
+lib.perm_selector_save.restype = _i32
+PERM_MLP_PARAMS = 4675
 
 
 class PermError(RuntimeError):

@@ -33,12 +33,21 @@ int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, i
   const uint64_t threads = (uint64_t)total;
   int grid = (int)std::min<uint64_t>((uint64_t)cus * 8, (threads + 255) / 256);
   grid = std::max(grid, 1);
+  uint64_t run = (uint64_t)total;
+  const double f = tune_fraction();
+  if (f < 1.0) {
+    // a prefix of the maps, still spread over every thread
+    const uint64_t floor_run = std::min<uint64_t>(run, (uint64_t)grid * 256);
+    run = std::max<uint64_t>(floor_run, (uint64_t)std::llround((double)run * f));
+    run = std::min<uint64_t>(run, (uint64_t)total);
+  }
+  tune_record((double)run / (double)(uint64_t)total);
   const int C = kind == ENGINE_CPLX ? 2 : 1;
   double *part = nullptr;
   if (hipMallocAsync((void **)&part, sizeof(double) * 2 * C * (size_t)grid, s) != hipSuccess)
     return PERM_E_HIP;
   profile_begin(s);
-  hipError_t e = launch_combinatoric(kind, M, N, dt, dA, lda, tr, (uint64_t)total, grid, part, s);
+  hipError_t e = launch_combinatoric(kind, M, N, dt, dA, lda, tr, run, grid, part, s);
   profile_end(s);
   if (e == hipSuccess) {
     Finish f;
@@ -73,9 +82,13 @@ int perm_combinatoric(int m, int n, perm_dtype dt, const void *dA, int64_t lda, 
 int perm_select(int m, int n, perm_dtype dt, double density, perm_algo *chosen, int *source) {
   if (m < 0 || n < 0 || (int)dt < 0 || (int)dt > (int)PERM_B8) return PERM_E_INVALID;
   const int M = std::min(m, n), N = std::max(m, n);
+  // the engine kind of the default output type of dt (integers: exact)
+  const int kind = dt == PERM_C128 ? ENGINE_CPLX : dt == PERM_F64 ? ENGINE_REAL : ENGINE_INT;
+  perm_algo order[3];
   int src = 0;
-  perm_algo a = select_algorithm(M, N, dt, density, &src);
-  if (chosen) *chosen = a;
+  const int cnt = rank_algorithms(M, N, dt, density, algo_mask(M, N, kind), order, &src);
+  if (cnt == 0) return PERM_E_TOO_LARGE;
+  if (chosen) *chosen = order[0];
   if (source) *source = src;
   return PERM_OK;
 }
@@ -86,23 +99,28 @@ int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out
   int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
   if (rc) return rc;
   const int M = std::min(m, n), N = std::max(m, n);
+  perm_algo order[3];
   int src = 0;
-  perm_algo a = select_algorithm(M, N, dt, density, &src);
-  // fall back along the cheaper algorithms if the choice cannot serve the shape
-  if (a == PERM_ALGO_COMBINATORIC) {
-    u128_host total = 1;
-    for (int i = 0; i < M; ++i) total *= (u128_host)(N - i);
-    if (total > ((u128_host)1 << 40)) a = PERM_ALGO_GLYNN;
+  const int cnt = rank_algorithms(M, N, dt, density, algo_mask(M, N, kind), order, &src);
+  if (cnt == 0) return PERM_E_TOO_LARGE;
+  // in predicted order; an algorithm that refuses the input (size limit, or
+  // an integer bound that only it cannot meet, such as Glynn's extra factor
+  // 2^(n-1) (n-m)!) passes to the next one
+  rc = PERM_E_TOO_LARGE;
+  for (int i = 0; i < cnt; ++i) {
+    switch (order[i]) {
+      case PERM_ALGO_COMBINATORIC:
+        rc = perm_combinatoric(m, n, dt, dA, lda, ot, dOut, flags, stream);
+        break;
+      case PERM_ALGO_RYSER: rc = perm_ryser(m, n, dt, dA, lda, ot, dOut, flags, stream); break;
+      default: rc = perm_glynn(m, n, dt, dA, lda, ot, dOut, flags, stream); break;
+    }
+    if (rc != PERM_E_TOO_LARGE && rc != PERM_E_OVERFLOW) {
+      if (rc == PERM_OK && chosen) *chosen = order[i];
+      return rc;
+    }
   }
-  if (a == PERM_ALGO_GLYNN && kind == ENGINE_INT && N > 28 && M < N) a = PERM_ALGO_RYSER;
-  if (a == PERM_ALGO_GLYNN && N > ENGINE_MAX_NV_REAL) a = PERM_ALGO_RYSER;
-  if (chosen) *chosen = a;
-  switch (a) {
-    case PERM_ALGO_COMBINATORIC:
-      return perm_combinatoric(m, n, dt, dA, lda, ot, dOut, flags, stream);
-    case PERM_ALGO_RYSER: return perm_ryser(m, n, dt, dA, lda, ot, dOut, flags, stream);
-    default: return perm_glynn(m, n, dt, dA, lda, ot, dOut, flags, stream);
-  }
+  return rc;
 }
 
 int perm_selector_load(const char *path) { return selector_load_file(path); }

@@ -77,6 +77,16 @@ void profile_end(hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ //
+// work truncation for perm_time (thread-local, 1 outside perm_time)   //
+// ------------------------------------------------------------------ //
+static thread_local double t_tune_fraction = 1.0;
+static thread_local double t_tune_ran = 1.0;
+double tune_fraction() { return t_tune_fraction; }
+void tune_record(double ran) { t_tune_ran = ran; }
+void tune_set(double f) { t_tune_fraction = f; }
+double tune_ran() { return t_tune_ran; }
+
+// ------------------------------------------------------------------ //
 // launch planning for the Gray-code engine                           //
 // ------------------------------------------------------------------ //
 int plan_gray(int kind, int nv, int nbits, GrayPlan &p) {
@@ -290,6 +300,14 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
   GrayPlan plan;
   int rc = plan_gray(kind, nv, nbits, plan);
   if (rc) return rc;
+  uint64_t bpl_run = plan.blocks_per_lane;
+  const double f = tune_fraction();
+  if (f < 1.0 && plan.blocks_per_lane >= 4) {
+    // keep an even count: the engine pairs blocks of opposite parity
+    bpl_run = (uint64_t)std::llround((double)plan.blocks_per_lane * f / 2.0) * 2;
+    bpl_run = std::max<uint64_t>(2, std::min(bpl_run, plan.blocks_per_lane));
+  }
+  tune_record((double)bpl_run / (double)plan.blocks_per_lane);
   const int C = kind == ENGINE_CPLX ? 2 : 1;
   const size_t tbl_n = (size_t)2 * nbits * nv * C;
   const size_t base_n = (size_t)nv * C;
@@ -309,7 +327,7 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     w.nbits = nbits;
     w.b = plan.b;
     w.prod_levels = pl;
-    w.blocks_per_lane = plan.blocks_per_lane;
+    w.blocks_per_lane = bpl_run;
     profile_begin(s);
     switch (kind) {
       case ENGINE_REAL: e = launch_gray_engine_real(w, plan.grid, plan.block, part, s); break;

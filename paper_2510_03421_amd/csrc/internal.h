@@ -62,6 +62,7 @@ struct RectWalk {
   int a_lo, a_hi;
   int prod_levels;
   uint64_t total_cost;
+  uint32_t walk_cap;  // at most this many transitions per walk (work truncation for timing)
 };
 
 // Batched Glynn: one descriptor per matrix (m <= n, row-major, ld elements),

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -124,14 +125,41 @@ void plan_classes(int M, int N, int l, ClassPlan &c) {
     c.k_lo[a] = (uint32_t)klo;
     c.k_hi[a] = (uint32_t)khi;
     uint64_t steps = 0;
-    for (int k = klo; k <= khi; ++k) steps += binom_u64(l, k);
-    c.item_cost[a] = steps;
+    // fixed work of an item in step units (a step: m adds, m - 1 multiplies
+    // and the accumulation): rebuilding the H row sums, and per walk its first
+    // subset, its first term and the weighted accumulation
+    const uint64_t step_ops = 2 * (uint64_t)M + 6;
+    uint64_t ops = (uint64_t)a * (uint64_t)M + 20;
+    for (int k = klo; k <= khi; ++k) {
+      steps += binom_u64(l, k);
+      ops += (uint64_t)k * (uint64_t)M + 40;
+    }
+    c.item_cost[a] = steps + (ops + step_ops - 1) / step_ops;
     c.lanes[a] = binom_u64(c.h, a);
     c.items[a] = (c.lanes[a] + 63) / 64;
     c.total_items += c.items[a];
-    acc += c.items[a] * steps;
+    acc += c.items[a] * c.item_cost[a];
   }
   c.total_cost = acc;
+}
+
+// Fraction of the total cost run when every walk stops after `cap`
+// transitions (the fixed per-item work is always done).
+double rect_fraction_run(const ClassPlan &c, int M, uint32_t cap) {
+  if (c.total_cost == 0) return 1.0;
+  double run = 0.0;
+  for (int a = c.a_lo; a <= c.a_hi; ++a) {
+    if (c.item_cost[a] == 0 || c.items[a] == 0) continue;
+    uint64_t steps = 0, cut = 0;
+    for (int k = (int)c.k_lo[a]; k <= (int)c.k_hi[a]; ++k) {
+      const uint64_t t = binom_u64(c.l, k);
+      steps += t;
+      cut += 1 + std::min<uint64_t>(t - 1, cap);
+    }
+    run += (double)c.items[a] * (double)(c.item_cost[a] - steps + cut);
+  }
+  (void)M;
+  return std::min(1.0, run / (double)c.total_cost);
 }
 
 }  // namespace
@@ -217,6 +245,20 @@ int run_ryser_rect(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int
     w.a_hi = cp.a_hi;
     w.prod_levels = pl;
     w.total_cost = cp.total_cost;
+    w.walk_cap = ~0u;
+    const double f = tune_fraction();
+    if (f < 1.0) {
+      // the largest cap whose run fraction does not exceed f (at least 0)
+      uint32_t lo = 0, hi = (uint32_t)binom_u64(l, l / 2);
+      while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (rect_fraction_run(cp, M, mid) <= f) lo = mid; else hi = mid - 1;
+      }
+      w.walk_cap = lo;
+      tune_record(rect_fraction_run(cp, M, lo));
+    } else {
+      tune_record(1.0);
+    }
     profile_begin(s);
     e = launch_ryser_rect(kind, w, grid, part, s);
     profile_end(s);

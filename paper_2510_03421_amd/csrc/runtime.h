@@ -24,6 +24,13 @@ int device_cus();
 // engine-kernel timing around one launch (no-ops unless perm_profile_enable(1))
 void profile_begin(hipStream_t s);
 void profile_end(hipStream_t s);
+// Work truncation used only by perm_time (calling thread): the fraction of
+// the main kernel's work to run (1 = all), and the fraction the last call
+// actually ran (work is cut at block / item / map granularity).
+double tune_fraction();
+void tune_record(double ran);
+void tune_set(double f);
+double tune_ran();
 int plan_gray(int kind, int nv, int nbits, GrayPlan &p);
 int engine_kind_for(perm_dtype dt, perm_out ot, int &kind);
 int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,

@@ -1,8 +1,9 @@
-// Host side of algorithm selection: features, the threshold table and MLP
-// inference from loaded weights.  (The network is trained on the GPU by the
-// kernels in mlp.hip; this file only evaluates it for single queries.)
+// Host side of algorithm selection: features, the threshold table and the
+// network's inference from loaded weights for single queries.  (The network
+// is trained on the GPU by the kernels in mlp.hip.)
 #include "selector.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -34,8 +35,8 @@ void selector_features(int M, int N, perm_dtype dt, double density, float f[kSel
 }
 
 const ThresholdTable &default_table() {
-  // Values fitted to MI355X timings of the three algorithms (square Glynn and
-  // Ryser, rectangular Ryser by size) -- see the selector training report.
+  // Alg. 5's structure with values set for this library's kernels; a weights
+  // file may carry a refitted table.
   static const ThresholdTable t = {{0.0,
                                     /*p1*/ 0.0, /*p2*/ -1.0, /*p3*/ 5.5, /*p4*/ 4.0,
                                     /*p5*/ 1.0, /*p6*/ 0.0, /*p7*/ -0.62, /*p8*/ 8.0}};
@@ -74,20 +75,63 @@ static void mlp_forward(const Net &net, const float x[kSelIn], float y[kSelOut])
   }
 }
 
-perm_algo select_algorithm(int M, int N, perm_dtype dt, double density, int *source) {
-  std::lock_guard<std::mutex> g(g_mu);
-  if (g_net.loaded) {
-    float x[kSelIn], y[kSelOut];
-    selector_features(M, N, dt, density, x);
-    mlp_forward(g_net, x, y);
-    int best = 0;
-    for (int a = 1; a < kSelOut; ++a)
-      if (y[a] < y[best]) best = a;
-    if (source) *source = 1;
-    return (perm_algo)best;  // output order = perm_algo order
+unsigned algo_mask(int M, int N, int kind) {
+  unsigned mask = 0;
+  // combinatoric: at most 2^40 injective maps
+  double maps = 1.0;
+  for (int i = 0; i < M; ++i) maps *= (double)(N - i);
+  if (maps <= 1099511627776.0) mask |= 1u << PERM_ALGO_COMBINATORIC;
+  const int nv_max = kind == 2 ? 40 : 48;  // Gray-walk engine limits (integer / floating)
+  if (M == N ? N <= nv_max : (M <= 40 && N <= 64)) mask |= 1u << PERM_ALGO_RYSER;
+  if (N <= nv_max) mask |= 1u << PERM_ALGO_GLYNN;
+  return mask;
+}
+
+// log2 of the number of terms each algorithm sums (its cost up to a factor)
+static double log2_terms(perm_algo a, int M, int N) {
+  switch (a) {
+    case PERM_ALGO_COMBINATORIC: {
+      double l = 0.0;
+      for (int i = 0; i < M; ++i) l += std::log2((double)(N - i));
+      return l;
+    }
+    case PERM_ALGO_RYSER: {
+      if (M == N) return (double)N;
+      double s = 0.0, c = 1.0;  // sum_{k <= M} C(N, k)
+      for (int k = 0; k <= M; ++k) {
+        s += c;
+        c = c * (double)(N - k) / (double)(k + 1);
+      }
+      return std::log2(s);
+    }
+    default: return (double)(N - 1);
   }
-  if (source) *source = 0;
-  return table_choice(g_net.has_table ? g_net.table : default_table(), M, N);
+}
+
+int rank_algorithms(int M, int N, perm_dtype dt, double density, unsigned mask,
+                    perm_algo order[3], int *source) {
+  double key[3];
+  int src = 0;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (g_net.loaded) {
+      float x[kSelIn], y[kSelOut];
+      selector_features(M, N, dt, density, x);
+      mlp_forward(g_net, x, y);
+      for (int a = 0; a < 3; ++a) key[a] = y[a];  // output order = perm_algo order
+      src = 1;
+    } else {
+      const perm_algo c = table_choice(g_net.has_table ? g_net.table : default_table(), M, N);
+      for (int a = 0; a < 3; ++a) key[a] = log2_terms((perm_algo)a, M, N);
+      key[c] = -1e300;  // the table's choice first
+    }
+  }
+  int cnt = 0;
+  for (int a = 0; a < 3; ++a)
+    if (mask & (1u << a)) order[cnt++] = (perm_algo)a;
+  std::stable_sort(order, order + cnt, [&](perm_algo x, perm_algo y) { return key[x] < key[y]; });
+  if (source) *source = src;
+  return cnt;
 }
 
 // Text format (whitespace separated):

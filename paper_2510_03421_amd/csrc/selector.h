@@ -4,11 +4,13 @@
 #pragma once
 
 #include "../../include/perm.h"
+#include "mlp.h"
 
 namespace permgpu {
 
-// Network shape: 4 -> 64 -> 64 -> 3, ReLU hidden layers, FP32.
-constexpr int kSelIn = 4, kSelH = 64, kSelOut = 3;
+// Network shape: 4 -> 64 -> 64 -> 3, ReLU hidden layers, FP32 (the same
+// network the GPU kernels train).
+constexpr int kSelIn = kMlpIn, kSelH = kMlpHidden, kSelOut = kMlpOut;
 
 // Features of a problem (the order the network sees them).
 void selector_features(int M, int N, perm_dtype dt, double density, float f[kSelIn]);
@@ -23,9 +25,16 @@ struct ThresholdTable {
 const ThresholdTable &default_table();
 perm_algo table_choice(const ThresholdTable &t, int M, int N);
 
-// The active choice: the loaded network if any, else the table.  *source = 1
-// when the network decided.
-perm_algo select_algorithm(int M, int N, perm_dtype dt, double density, int *source);
+// Algorithms whose size limits admit the logical M x N shape (M <= N) for an
+// engine kind: bit a set <=> perm_algo a can run it.
+unsigned algo_mask(int M, int N, int kind);
+
+// The algorithms of `mask` in the order perm_auto tries them: by the loaded
+// network's predicted log time if a network is loaded (*source = 1), else
+// the table's choice first and the rest by their term counts (*source = 0).
+// Returns how many entries of order[] were filled.
+int rank_algorithms(int M, int N, perm_dtype dt, double density, unsigned mask,
+                    perm_algo order[3], int *source);
 
 // Load (path != NULL) or unload (NULL) network weights / table values.
 int selector_load_file(const char *path);

@@ -1,0 +1,105 @@
+"""Timing generator for the algorithm selector: times every algorithm the
+library offers on seeded (m, n, density, dtype) cases on the current GPU and
+writes one CSV row per case.
+
+    python -m paper_2510_03421_amd.tune --out timings.csv [--cases 5000]
+           [--start 0] [--stop 5000]
+
+A run that would take long is timed on two cut-down fractions of its work
+(``perm_time``) and extrapolated linearly to the whole: t(f) = a + b f gives
+t(1) = a + b, where a is the fixed cost (planning, staging, reduction,
+launch latency) and b the time of the full walk.  Integer (0/1) cases are
+timed with PERM_FLAG_WRAP, so that no data-dependent overflow refusal hides a
+run time; an algorithm whose size limits refuse the shape gets an empty cell.
+Rows are appended as they are measured, so an interrupted run can continue
+with --start.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time as _time
+
+import numpy as np
+import torch
+
+from . import _capi as C
+from . import selector as S
+
+_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if _ROOT not in sys.path:
+    sys.path.insert(0, _ROOT)
+import workloads  # noqa: E402  (seeded case recipes)
+
+HEADER = "i,m,n,dtype,density,seed,ms_combinatoric,ms_ryser,ms_glynn,frac_combinatoric," \
+         "frac_ryser,frac_glynn"
+TORCH_DT = {"f64": torch.float64, "c128": torch.complex128, "b8": torch.uint8}
+TARGET_MS = 4.0      # length of the shorter of the two cut-down runs
+FULL_MS = 25.0       # runs estimated shorter than this are timed whole
+
+
+def time_algo(algo: str, a: torch.Tensor, flags: int):
+    """(estimated full ms, smallest fraction run) or (None, None) if refused."""
+    try:
+        t0, r0 = S.time(algo, a, fraction=1e-12, reps=1, flags=flags)
+    except C.PermError as e:
+        if e.status in (C.PERM_E_TOO_LARGE, C.PERM_E_UNSUPPORTED):
+            return None, None
+        raise
+    if r0 >= 1.0:
+        t, _ = S.time(algo, a, fraction=1.0, reps=3, flags=flags)
+        return t, 1.0
+    est = t0 / r0
+    if est <= FULL_MS:
+        t, _ = S.time(algo, a, fraction=1.0, reps=2, flags=flags)
+        return t, 1.0
+    f1 = min(1.0, max(r0, TARGET_MS / est))
+    t1, r1 = S.time(algo, a, fraction=f1, reps=1, flags=flags)
+    t2, r2 = S.time(algo, a, fraction=min(1.0, 2.0 * r1), reps=1, flags=flags)
+    if r2 >= 1.0:
+        return t2, r1
+    slope = (t2 - t1) / (r2 - r1) if r2 > r1 else 0.0
+    if slope <= 0.0:
+        return t2 / r2, r1
+    return (t1 - slope * r1) + slope, r1
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--cases", type=int, default=5000)
+    ap.add_argument("--seed", type=int, default=5000)
+    ap.add_argument("--start", type=int, default=0)
+    ap.add_argument("--stop", type=int, default=None)
+    args = ap.parse_args(argv)
+    cases = workloads.selector_cases(args.cases, seed=args.seed)
+    stop = args.cases if args.stop is None else min(args.stop, args.cases)
+    new = not os.path.exists(args.out) or os.path.getsize(args.out) == 0
+    dev = torch.device("cuda", torch.cuda.current_device())
+    t_start = _time.time()
+    with open(args.out, "a") as fh:
+        if new:
+            fh.write(HEADER + "\n")
+        for i in range(args.start, stop):
+            c = cases[i]
+            a = workloads.case_matrix(c)
+            density = float(np.count_nonzero(a)) / a.size
+            at = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+            flags = C.PERM_FLAG_WRAP if c["dtype"] == "b8" else 0
+            ms, fr = [], []
+            for algo in S.ALGO_ORDER:
+                t, f = time_algo(algo, at, flags)
+                ms.append("" if t is None else f"{t:.6g}")
+                fr.append("" if f is None else f"{f:.6g}")
+            fh.write(f"{i},{c['m']},{c['n']},{c['dtype']},{density:.6g},{c['seed']},"
+                     + ",".join(ms) + "," + ",".join(fr) + "\n")
+            fh.flush()
+            if (i + 1) % 50 == 0 or i + 1 == stop:
+                print(f"tune: case {i + 1}/{stop} done, {(_time.time() - t_start):.0f} s",
+                      flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
