@@ -208,7 +208,10 @@ int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const in
  * form, and runs the first one that accepts the input. */
 
 /* Load selector weights (the text format written by perm_selector_save);
- * path NULL unloads them (perm_auto then uses the threshold table).
+ * path NULL unloads them (perm_auto then uses the threshold table).  Weights
+ * trained on MI355X timings ship as selector_weights.txt beside the library
+ * (the Python binding loads them at import); without them the built-in table
+ * holds values fitted to the same timings.
  * PERM_E_INVALID if the file cannot be read or is malformed (the previous
  * weights stay loaded). */
 int perm_selector_load(const char *path);
@@ -230,12 +233,13 @@ int perm_selector_features(int m, int n, perm_dtype dt, double density, float *x
  * on `stream`, waiting for the stream after each run, and returns in *ms the
  * median host wall time (call to completion) of the last reps runs.  With
  * fraction < 1 the algorithm's main kernel does only about that fraction of
- * its work so that a caller can extrapolate the time of a long run from short
- * ones: Glynn and square Ryser run fewer Gray-code blocks per lane (never
- * fewer than two), rectangular Ryser stops every revolving-door walk after a
- * cap on its transitions (every subset of the lane part is still visited),
- * the combinatoric sum runs a prefix of the maps.  *fraction_run (may be
- * NULL) receives the fraction of the work actually run.  The value computed
+ * the work of each lane or wave, so that a caller can extrapolate the time of
+ * a long run from short ones (the time is about a + b x for the fraction x
+ * run): Glynn and square Ryser run fewer Gray-code blocks per lane (never
+ * fewer than two), in rectangular Ryser every wave stops after that fraction
+ * of its share of the work (its last item's walks cut short), the
+ * combinatoric sum runs a prefix of the maps.  *fraction_run (may be NULL)
+ * receives the fraction x actually run.  The value computed
  * is discarded.  Errors: those of the algorithm's entry point, and
  * PERM_E_INVALID for fraction outside (0, 1], reps < 1 or ms NULL.
  * Synchronous. */

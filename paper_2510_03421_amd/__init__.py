@@ -13,6 +13,7 @@ library; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import torch
 
@@ -140,6 +141,13 @@ def select(m: int, n: int, dtype: torch.dtype = torch.float64, density: float = 
 
 def selector_load(path: str | None) -> None:
     C.check(C.lib.perm_selector_load(path.encode() if path else None), "perm_selector_load")
+
+
+# Selector weights trained on MI355X timings ship beside the library; perm_auto
+# uses them from import on (selector_load(None) returns to the table).
+SELECTOR_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.txt")
+if os.path.exists(SELECTOR_WEIGHTS):
+    C.check(C.lib.perm_selector_load(SELECTOR_WEIGHTS.encode()), "perm_selector_load")
 
 
 def value(r: Result):

@@ -62,7 +62,10 @@ struct RectWalk {
   int a_lo, a_hi;
   int prod_levels;
   uint64_t total_cost;
-  uint32_t walk_cap;  // at most this many transitions per walk (work truncation for timing)
+  // Cut-down runs (timing only): each wave stops after about
+  // range * cut_q / 2^32 cost units of its range, running the walks of its
+  // last item only in part.  2^32 = everything.
+  uint64_t cut_q;
 };
 
 // Batched Glynn: one descriptor per matrix (m <= n, row-major, ld elements),

@@ -143,25 +143,6 @@ void plan_classes(int M, int N, int l, ClassPlan &c) {
   c.total_cost = acc;
 }
 
-// Fraction of the total cost run when every walk stops after `cap`
-// transitions (the fixed per-item work is always done).
-double rect_fraction_run(const ClassPlan &c, int M, uint32_t cap) {
-  if (c.total_cost == 0) return 1.0;
-  double run = 0.0;
-  for (int a = c.a_lo; a <= c.a_hi; ++a) {
-    if (c.item_cost[a] == 0 || c.items[a] == 0) continue;
-    uint64_t steps = 0, cut = 0;
-    for (int k = (int)c.k_lo[a]; k <= (int)c.k_hi[a]; ++k) {
-      const uint64_t t = binom_u64(c.l, k);
-      steps += t;
-      cut += 1 + std::min<uint64_t>(t - 1, cap);
-    }
-    run += (double)c.items[a] * (double)(c.item_cost[a] - steps + cut);
-  }
-  (void)M;
-  return std::min(1.0, run / (double)c.total_cost);
-}
-
 }  // namespace
 
 int run_ryser_rect(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
@@ -245,17 +226,12 @@ int run_ryser_rect(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int
     w.a_hi = cp.a_hi;
     w.prod_levels = pl;
     w.total_cost = cp.total_cost;
-    w.walk_cap = ~0u;
+    w.cut_q = 1ull << 32;
     const double f = tune_fraction();
     if (f < 1.0) {
-      // the largest cap whose run fraction does not exceed f (at least 0)
-      uint32_t lo = 0, hi = (uint32_t)binom_u64(l, l / 2);
-      while (lo < hi) {
-        const uint32_t mid = lo + (hi - lo + 1) / 2;
-        if (rect_fraction_run(cp, M, mid) <= f) lo = mid; else hi = mid - 1;
-      }
-      w.walk_cap = lo;
-      tune_record(rect_fraction_run(cp, M, lo));
+      // every wave stops after about f of its share, whatever its items
+      w.cut_q = std::max<uint64_t>(1, (uint64_t)std::ldexp(f, 32));
+      tune_record(std::ldexp((double)w.cut_q, -32));
     } else {
       tune_record(1.0);
     }

@@ -205,4 +205,26 @@ def test_auto_moves_on_when_glynn_refuses_an_integer_bound():
         assert r.value() == math.factorial(30) // math.factorial(10)
         assert pg.ALGORITHMS[r.algo] != "glynn"
     finally:
-        pg.selector_load(None)
+        pg.selector_load(pg.SELECTOR_WEIGHTS)
+
+
+def test_training_on_stored_timings_beats_the_table():
+    """The network trained here, on the GPU, from the committed MI355X timings
+    (training split only) chooses better on the held-out split than the
+    threshold table does."""
+    import paper_2510_03421_amd as pg
+    from paper_2510_03421_amd import selector as S, train_selector as TS
+    d = TS.load_timings(os.path.join(os.path.dirname(pg.__file__), "data",
+                                     "selector_timings_mi355x.csv"))
+    tr, te = TS.split(len(d["m"]))
+    params, norm, hist = S.train(TS.features(d, tr), np.log(d["ms"][tr]).astype(np.float32),
+                                 epochs=3000, lr=3e-3, seed=1)
+    assert hist[-1] < 0.01 * hist[0]
+    path = os.path.join(tempfile.mkdtemp(), "w.txt")
+    S.save(path, params, norm)
+    try:
+        mlp = TS.regret(TS.library_choices(d, te, path), d["ms"][te])
+        table = TS.regret(TS.library_choices(d, te, None), d["ms"][te])
+    finally:
+        pg.selector_load(pg.SELECTOR_WEIGHTS)
+    assert np.mean(mlp) < np.mean(table), (np.mean(mlp), np.mean(table))

@@ -72,7 +72,7 @@ def test_table_mirror_matches_the_library(seed):
     try:
         got = np.array([lib_select(int(m), int(n), C.PERM_F64)[1] for m, n in zip(ms, ns)])
     finally:
-        pg.selector_load(None)
+        pg.selector_load(pg.SELECTOR_WEIGHTS)
     assert np.array_equal(got, want), np.flatnonzero(got != want)[:10]
 
 
@@ -98,3 +98,48 @@ def test_weights_file_round_trip():
         fh.write("permgpu-selector 1\nmlp 1 2 3\n")
     with pytest.raises(pg.PermError):
         pg.selector_load(bad)
+
+
+TIMINGS = os.path.join(os.path.dirname(pg.__file__), "data", "selector_timings_mi355x.csv")
+
+
+def test_shipped_network_beats_the_table_on_held_out_timings():
+    """On the 1000 held-out cases of the committed MI355X timings (5000 seeded
+    cases, 80/20 split), the shipped network's choices (made by perm_select
+    with its weights loaded) cost less time than the fitted table's, which
+    cost less than always running Glynn.  Regret = t_chosen / t_best - 1
+    against exhaustive timing of every algorithm."""
+    d = TS.load_timings(TIMINGS)
+    assert len(d["m"]) == 5000
+    _, te = TS.split(len(d["m"]))
+    ms = d["ms"][te]
+    try:
+        mlp = TS.regret(TS.library_choices(d, te, pg.SELECTOR_WEIGHTS), ms)
+        table = TS.regret(TS.library_choices(d, te, None), ms)
+    finally:
+        pg.selector_load(pg.SELECTOR_WEIGHTS)
+    avail = ~np.isnan(ms)
+    glynn = TS.regret(np.where(avail[:, 2], 2, np.where(avail[:, 1], 1, 0)), ms)
+    assert np.mean(mlp) < 0.03 and np.percentile(mlp, 95) < 0.1
+    assert np.mean(mlp) < 0.5 * np.mean(table)
+    assert np.mean(table) < np.mean(glynn)
+    assert np.mean(mlp <= 1e-12) > 0.9          # the fastest algorithm in > 90% of cases
+
+
+def test_committed_timings_are_consistent():
+    d = TS.load_timings(TIMINGS)
+    assert np.all(d["m"] <= d["n"]) and d["m"].min() >= 2 and d["n"].max() <= 48
+    avail = ~np.isnan(d["ms"])
+    assert np.all(avail.any(axis=1))
+    assert np.all(d["ms"][avail] > 0)
+    # availability is exactly the library's size limits (perm_select never
+    # picks an algorithm without a timing)
+    pg.selector_load(None)
+    try:
+        for i in range(0, 5000, 37):
+            m, n = int(d["m"][i]), int(d["n"][i])
+            dt = {"f64": C.PERM_F64, "c128": C.PERM_C128, "b8": C.PERM_B8}[d["dtype"][i]]
+            rc, ch, _ = lib_select(m, n, dt, float(d["density"][i]))
+            assert rc == 0 and avail[i, ch]
+    finally:
+        pg.selector_load(pg.SELECTOR_WEIGHTS)
