@@ -77,6 +77,8 @@ def _terms(algo, m, n):
         return 2 ** (n - 1)
     if algo == "ryser":
         return 2 ** n if m == n else sum(comb(n, s) for s in range(1, m + 1))
+    if algo == "glynn_esym":
+        return 2 ** (m - 1)
     from math import perm
     return perm(n, m)
 
@@ -92,12 +94,16 @@ def suite(args):
     runs = [("u12", "glynn", None), ("u12", "ryser", None), ("u12", "combinatoric", None),
             ("u32", "glynn", None), ("u32", "ryser", None), ("c32", "glynn", None),
             ("b28", "ryser", "i128"), ("b28", "glynn", "i128"), ("b30", "ryser", "i128"),
-            ("u20x40", "ryser", None), ("u20x40", "glynn", None),
-            ("b16x48", "ryser", "i128"), ("u36", "glynn", "dd")]
-    fn = {"glynn": pg.glynn, "ryser": pg.ryser, "combinatoric": pg.combinatoric}
+            ("u20x40", "ryser", None), ("u20x40", "glynn", None), ("u20x40", "glynn_esym", None),
+            ("b16x48", "ryser", "i128"), ("b16x48", "glynn_esym", "f64"), ("u36", "glynn", "dd")]
+    fn = {"glynn": pg.glynn, "ryser": pg.ryser, "combinatoric": pg.combinatoric,
+          "glynn_esym": pg.glynn_esym}
     pg.profile_enable(True)
     for name, algo, out in runs:
-        a = torch.from_numpy(workloads.config_matrix(name)).cuda()
+        a = workloads.config_matrix(name)
+        if algo == "glynn_esym" and out == "f64":
+            a = a.astype(np.float64)     # the e_m form computes in floating point
+        a = torch.from_numpy(a).cuda()
         m, n = a.shape
         terms = _terms(algo, m, n)
         r = fn[algo](a, out=out)
@@ -116,7 +122,9 @@ def suite(args):
         err = None
         if rec is not None:
             ref = rec["value"]
-            if isinstance(ref, str):
+            if isinstance(ref, str) and isinstance(val, float):
+                err = abs(val - int(ref)) / abs(int(ref)) if int(ref) else abs(val)
+            elif isinstance(ref, str):
                 err = 0 if int(ref) == val else abs(int(ref) - val)
             elif "hi" in ref:
                 err = abs(val - (ref["hi"] + ref["lo"])) / abs(ref["hi"] + ref["lo"])

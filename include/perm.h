@@ -128,6 +128,19 @@ int perm_profile_last(double *ms);
 int perm_glynn(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                void *dOut, uint32_t flags, void *stream);
 
+/* perm_glynn_esym -- the rectangular Glynn sum with its padding rows summed
+ * out.  The n - m rows of ones that Eq. glynn_filled_matrix appends are
+ * identical, and summing their signs leaves
+ *   per(A) = 2^-(m-1) sum_{delta in {+-1}^m, delta_1=+1} (prod delta) e_m(c(delta)),
+ *   c_j = sum_i delta_i a_ij,
+ * with e_m the m-th elementary symmetric polynomial of c_1..c_n (expanding
+ * e_m into row choices, the sign sum keeps the products that use every row
+ * once).  Cost 2^(m-1) terms of O(n min(m, 32)) instead of Glynn's 2^(n-1)
+ * terms for m < n.  Floating-point outputs only (PERM_E_UNSUPPORTED for
+ * PERM_OUT_I64 / PERM_OUT_I128).  Limits: min(m, n) <= 32, max(m, n) <= 48. */
+int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+                    void *dOut, uint32_t flags, void *stream);
+
 /* perm_ryser -- Ryser's inclusion-exclusion formula, Sec. 1.2
  * Eq. ryser_square (m = n) and Eq. ryser_rectangle (m < n, read over column
  * subsets of size m-k with weight (-1)^k C(n-m+k, k)).  Square: Gray-code

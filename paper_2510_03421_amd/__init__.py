@@ -20,7 +20,7 @@ import torch
 from . import _capi as C
 from ._capi import PermError
 
-__all__ = ["glynn", "ryser", "combinatoric", "auto", "value", "PermError", "BatchPlan",
+__all__ = ["glynn", "glynn_esym", "ryser", "combinatoric", "auto", "value", "PermError", "BatchPlan",
            "glynn_batched", "select", "selector_load", "ALGORITHMS", "version",
            "profile_enable", "profile_last_ms"]
 
@@ -111,6 +111,12 @@ def glynn(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:
 def ryser(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:
     """Ryser's formula (square; rectangular by subset size)."""
     return _run(C.lib.perm_ryser, a, out, flags)
+
+
+def glynn_esym(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:
+    """Rectangular Glynn with the padding rows summed out: a sum over the signs
+    of the m rows of e_m of the column sums (floating-point outputs)."""
+    return _run(C.lib.perm_glynn_esym, a, out, flags)
 
 
 def combinatoric(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:

@@ -32,7 +32,7 @@ _i32, _i64, _u32, _p, _d = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes
     ctypes.c_double
 
 _single = [_i32, _i32, _i32, _p, _i64, _i32, _p, _u32, _p]
-for _name in ("perm_glynn", "perm_ryser", "perm_combinatoric"):
+for _name in ("perm_glynn", "perm_ryser", "perm_combinatoric", "perm_glynn_esym"):
     getattr(lib, _name).argtypes = _single
     getattr(lib, _name).restype = _i32
 lib.perm_auto.argtypes = _single + [_d, ctypes.POINTER(_i32)]

@@ -96,6 +96,12 @@ int plan_gray(int kind, int nv, int nbits, GrayPlan &p) {
     case ENGINE_CPLX: bpc = gray_engine_blocks_per_cu_cplx(nv); break;
     default: bpc = gray_engine_blocks_per_cu_int(nv); break;
   }
+  return plan_gray_bpc(bpc, nbits, p);
+}
+
+// The plan for a walk whose kernel keeps `bpc` 256-thread workgroups resident
+// per compute unit.
+int plan_gray_bpc(int bpc, int nbits, GrayPlan &p) {
   const int cus = device_cus();
   if (bpc <= 0 || cus <= 0) return PERM_E_HIP;
   const uint64_t lanes_max = pow2_floor((uint64_t)cus * (uint64_t)bpc * 256u);
@@ -349,6 +355,65 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
   return e == hipSuccess ? PERM_OK : PERM_E_HIP;
 }
 
+// ------------------------------------------------------------------ //
+// the e_m form of the rectangular Glynn sum                          //
+// ------------------------------------------------------------------ //
+int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
+             void *dOut, hipStream_t s, int kind) {
+  if (kind == ENGINE_INT) return PERM_E_UNSUPPORTED;
+  if (M > ESYM_MAX_M || N > 48) return PERM_E_TOO_LARGE;
+  const int nv = N, nbits = M - 1;
+  const int bpc = kind == ENGINE_CPLX ? esym_blocks_per_cu_cplx(nv) : esym_blocks_per_cu_real(nv);
+  GrayPlan plan;
+  int rc = plan_gray_bpc(bpc, nbits, plan);
+  if (rc) return rc;
+  uint64_t bpl_run = plan.blocks_per_lane;
+  const double f = tune_fraction();
+  if (f < 1.0 && plan.blocks_per_lane >= 4) {
+    bpl_run = (uint64_t)std::llround((double)plan.blocks_per_lane * f / 2.0) * 2;
+    bpl_run = std::max<uint64_t>(2, std::min(bpl_run, plan.blocks_per_lane));
+  }
+  tune_record((double)bpl_run / (double)plan.blocks_per_lane);
+  const int C = kind == ENGINE_CPLX ? 2 : 1;
+  const size_t tbl_n = (size_t)2 * nbits * nv * C;
+  const size_t base_n = (size_t)nv * C;
+  const size_t part_n = (size_t)plan.grid * 2 * C;
+  char *scratch = nullptr;
+  if (hipMallocAsync((void **)&scratch, sizeof(double) * (tbl_n + base_n + part_n) + 256, s) !=
+      hipSuccess)
+    return PERM_E_HIP;
+  double *tbl = (double *)scratch;
+  double *base = tbl + tbl_n;
+  double *part = base + base_n;
+  hipError_t e = launch_stage_gray(2, M, N, dt, dA, lda, tr, tbl, base, C == 2, s);
+  if (e == hipSuccess) {
+    GrayWalk w;
+    w.tbl = tbl;
+    w.base = base;
+    w.nv = nv;
+    w.nbits = nbits;
+    w.b = plan.b;
+    w.prod_levels = 0;
+    w.blocks_per_lane = bpl_run;
+    w.m = M;
+    profile_begin(s);
+    e = kind == ENGINE_CPLX ? launch_esym_cplx(w, plan.grid, plan.block, part, s)
+                            : launch_esym_real(w, plan.grid, plan.block, part, s);
+    profile_end(s);
+  }
+  if (e == hipSuccess) {
+    Finish fin;
+    fin.mode = FINISH_GLYNN;  // E / 2^(M-1): no padding rows
+    fin.m = M;
+    fin.n = M;
+    fin.ot = ot;
+    e = launch_finish(kind, part, plan.grid, fin, dOut, s);
+  }
+  hipError_t e2 = hipFreeAsync(scratch, s);
+  if (e == hipSuccess) e = e2;
+  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+}
+
 }  // namespace permgpu
 
 // ==================================================================== //
@@ -396,6 +461,19 @@ int perm_glynn(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_ou
   if (M == 0) return launch_write_one(ot, dOut, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
   if (N > kMaxN) return PERM_E_TOO_LARGE;
   return run_gray(0, M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind);
+}
+
+int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+                    void *dOut, uint32_t flags, void *stream) {
+  (void)flags;
+  int kind = 0;
+  int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int tr = m > n;
+  const int M = std::min(m, n), N = std::max(m, n);
+  if (M == 0) return launch_write_one(ot, dOut, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
+  return run_esym(M, N, dt, dA, lda, tr, ot, dOut, s, kind);
 }
 
 int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,

@@ -1,5 +1,5 @@
-// Routes a Gray-walk launch to the translation unit that instantiates its
-// vector length.
+// Routes a Gray-walk launch (engine or e_m form) to the translation unit that
+// instantiates its vector length.
 #include "internal.h"
 
 namespace permgpu {
@@ -69,6 +69,38 @@ hipError_t launch_gray_engine_int(const GrayWalk &w, int grid, int block, void *
   if (w.nv >= 17 && w.nv <= 26) return gray_launch_int_b(w, grid, block, partials, s);
   if (w.nv >= 27 && w.nv <= 34) return gray_launch_int_c(w, grid, block, partials, s);
   if (w.nv >= 35 && w.nv <= 40) return gray_launch_int_d(w, grid, block, partials, s);
+  return hipErrorInvalidValue;
+}
+
+int esym_occ_real_a(int nv);
+int esym_occ_real_b(int nv);
+int esym_occ_cplx_a(int nv);
+int esym_occ_cplx_b(int nv);
+hipError_t esym_launch_real_a(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+hipError_t esym_launch_real_b(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+hipError_t esym_launch_cplx_a(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+hipError_t esym_launch_cplx_b(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+
+int esym_blocks_per_cu_real(int nv) {
+  if (nv >= 1 && nv <= 24) return esym_occ_real_a(nv);
+  if (nv >= 25 && nv <= 48) return esym_occ_real_b(nv);
+  return 0;
+}
+int esym_blocks_per_cu_cplx(int nv) {
+  if (nv >= 1 && nv <= 24) return esym_occ_cplx_a(nv);
+  if (nv >= 25 && nv <= 48) return esym_occ_cplx_b(nv);
+  return 0;
+}
+hipError_t launch_esym_real(const GrayWalk &w, int grid, int block, void *partials,
+                            hipStream_t s) {
+  if (w.nv >= 1 && w.nv <= 24) return esym_launch_real_a(w, grid, block, partials, s);
+  if (w.nv >= 25 && w.nv <= 48) return esym_launch_real_b(w, grid, block, partials, s);
+  return hipErrorInvalidValue;
+}
+hipError_t launch_esym_cplx(const GrayWalk &w, int grid, int block, void *partials,
+                            hipStream_t s) {
+  if (w.nv >= 1 && w.nv <= 24) return esym_launch_cplx_a(w, grid, block, partials, s);
+  if (w.nv >= 25 && w.nv <= 48) return esym_launch_cplx_b(w, grid, block, partials, s);
   return hipErrorInvalidValue;
 }
 

@@ -48,6 +48,7 @@ struct GrayWalk {
   int b;               // log2 of the per-lane block length
   int prod_levels;     // ENGINE_INT only: exact binary64 product-tree depth
   uint64_t blocks_per_lane;
+  int m;               // e_m walk only: the degree (number of rows)
 };
 
 // Rectangular Ryser by subset size (see ryser_rect.hip for the layout).
@@ -112,8 +113,10 @@ struct Finish {
 };
 
 // ---- launchers (each returns a hipError_t) ----
-// Stage A into the update table of a Glynn walk (padded rows of ones for m<n)
-// or a square Ryser walk; converts the input dtype; `tr` reads A^T.
+// Stage A into the update table of a Glynn walk (algo 0: padded rows of ones
+// for m<n), a square Ryser walk (algo 1) or a walk over the signs of the m
+// rows only (algo 2, for the e_m form); converts the input dtype; `tr` reads
+// A^T.
 hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
                              int tr, double *tbl, double *base, int cplx, hipStream_t s);
 
@@ -130,6 +133,18 @@ hipError_t launch_gray_engine_int(const GrayWalk &w, int grid, int block, void *
 int gray_engine_blocks_per_cu_real(int nv);
 int gray_engine_blocks_per_cu_cplx(int nv);
 int gray_engine_blocks_per_cu_int(int nv);
+
+// The e_m form of the rectangular Glynn sum (esym.inc): the walk over the
+// signs of rows 1..m-1 with the n column sums as its vector (w.nv = n,
+// w.nbits = m-1, w.m = m <= ESYM_MAX_M); each term is +-e_m(v).  Partials as
+// the real / complex engine.
+#define ESYM_MAX_M 32
+hipError_t launch_esym_real(const GrayWalk &w, int grid, int block, void *partials,
+                            hipStream_t s);
+hipError_t launch_esym_cplx(const GrayWalk &w, int grid, int block, void *partials,
+                            hipStream_t s);
+int esym_blocks_per_cu_real(int nv);
+int esym_blocks_per_cu_cplx(int nv);
 
 // Single-workgroup deterministic reduction of `count` partials, scaling, and
 // the typed write of the result.

@@ -32,6 +32,7 @@ void tune_record(double ran);
 void tune_set(double f);
 double tune_ran();
 int plan_gray(int kind, int nv, int nbits, GrayPlan &p);
+int plan_gray_bpc(int bpc, int nbits, GrayPlan &p);
 int engine_kind_for(perm_dtype dt, perm_out ot, int &kind);
 int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,
              int &kind);
@@ -43,6 +44,8 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
              perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
 int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
                      perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
+int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
+             void *dOut, hipStream_t s, int kind);
 int run_ryser_rect(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
                    void *dOut, uint32_t flags, hipStream_t s, int kind);
 

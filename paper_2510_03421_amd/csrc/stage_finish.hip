@@ -26,15 +26,17 @@ __device__ __forceinline__ void read_entry(perm_dtype dt, const void *dA, int64_
 // algo 0 (Glynn): NV = n, nbits = n-1, padded matrix a' (rows m..n-1 are ones),
 //   base_j = sum_i a'_ij, U[q]_j = -2 a'_{q+1, j}.
 // algo 1 (square Ryser): NV = m, nbits = n, base = 0, U[q]_i = a_{i, q}.
+// algo 2 (signs of the m rows only, no padding): NV = n, nbits = m-1,
+//   base_j = sum_{i<m} a_ij, U[q]_j = -2 a_{q+1, j}.
 __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const void *dA,
                                   int64_t lda, int tr, double *tbl, double *base, int C) {
-  const int nv = algo == 0 ? n : m;
-  const int nbits = algo == 0 ? n - 1 : n;
+  const int nv = algo == 1 ? m : n;
+  const int nbits = algo == 0 ? n - 1 : (algo == 1 ? n : m - 1);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < nbits * nv) {
     const int q = idx / nv, j = idx % nv;
     double re, im;
-    if (algo == 0) {
+    if (algo != 1) {
       if (q + 1 < m) {
         read_entry(dt, dA, lda, tr, q + 1, j, re, im);
       } else {
@@ -57,8 +59,8 @@ __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const v
   }
   if (idx < nv) {
     double sr = 0.0, si = 0.0;
-    if (algo == 0) {
-      for (int i = 0; i < n; ++i) {
+    if (algo != 1) {
+      for (int i = 0; i < (algo == 0 ? n : m); ++i) {
         double re = 1.0, im = 0.0;
         if (i < m) read_entry(dt, dA, lda, tr, i, idx, re, im);
         sr += re;
@@ -273,8 +275,8 @@ __global__ void stage_rect_kernel(int m, int n, int l, perm_dtype dt, const void
 
 hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
                              int tr, double *tbl, double *base, int cplx, hipStream_t s) {
-  const int nv = algo == 0 ? n : m;
-  const int nbits = algo == 0 ? n - 1 : n;
+  const int nv = algo == 1 ? m : n;
+  const int nbits = algo == 0 ? n - 1 : (algo == 1 ? n : m - 1);
   int work = nbits * nv > nv ? nbits * nv : nv;
   if (work < 1) work = 1;
   const int threads = 256, blocks = (work + threads - 1) / threads;

@@ -1,0 +1,107 @@
+"""The e_m form of the rectangular Glynn sum (perm_glynn_esym) against the
+oracle: exact on integer-valued inputs that stay below 2^53, within the
+rounding bound of the formula on real and complex inputs, and at full size
+on the 20x40 and 16x48 workloads."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import dev, golden, ref_value, abs_ref
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def run(a, out=None):
+    import paper_2510_03421_amd as pg
+    return pg.glynn_esym(dev(a), out=out).value()
+
+
+def esym_abs_sum(a):
+    """2^-(m-1) sum over sign vectors (delta_1 = +1) of e_m(|c(delta)|), c the
+    column sums: each term of the formula is evaluated with a relative error
+    of a few n u against this scale."""
+    m, n = a.shape
+    tot = 0.0
+    for bits in range(2 ** (m - 1)):
+        d = np.array([1] + [(-1) ** ((bits >> i) & 1) for i in range(m - 1)])
+        c = np.abs(d @ a)
+        e = np.zeros(m + 1)
+        e[0] = 1.0
+        for j in range(n):
+            e[1:] = e[1:] + c[j] * e[:-1]
+        tot += e[m]
+    return tot / 2 ** (m - 1)
+
+
+SHAPES = [(m, n) for n in range(1, 9) for m in range(1, n + 1)]
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_small_integer_valued_exact(m, n):
+    rng = np.random.default_rng(300 * m + n)
+    a = rng.integers(-3, 4, size=(m, n))
+    want = oracle.per_brute(a.astype(np.int64))
+    assert run(a.astype(np.float64)) == float(want)
+    assert run(np.ascontiguousarray(a.T).astype(np.float64)) == float(want)   # m > n
+    z = a.astype(np.complex128) * (1 - 2j)
+    assert run(z) == complex(want * (1 - 2j) ** m)
+
+
+@pytest.mark.parametrize("m,n,seed", [(3, 11, 1), (6, 14, 2), (9, 20, 3), (12, 24, 4), (12, 12, 5),
+                                      (5, 40, 6), (1, 30, 7)])
+def test_random_against_oracle(m, n, seed):
+    a = workloads.uniform(m, n, 9100 + seed)
+    ref = oracle.per_laplace(a)
+    want = ref.hi + ref.lo
+    got = run(a)
+    bound = 8 * n * U * esym_abs_sum(a) + 4 * U * abs(want)
+    assert abs(got - want) <= bound, (got, want, bound)
+    z = workloads.complex_gauss(m, n, 9200 + seed)
+    refz = oracle.per_laplace(z)
+    wz = complex(refz.re.hi + refz.re.lo, refz.im.hi + refz.im.lo)
+    gz = run(z)
+    bz = 16 * n * U * esym_abs_sum(np.abs(z)) + 4 * U * abs(wz)
+    assert abs(gz - wz) <= bz, (gz, wz, bz)
+
+
+def test_u20x40_full_size():
+    rec = golden()["u20x40"]
+    a = workloads.config_matrix("u20x40")
+    want = ref_value(rec)
+    got = run(a)
+    assert abs(got - want) <= 1e-11 * abs_ref(rec)        # the accuracy criterion
+    assert abs(got - want) <= 1e-12 * abs(want)            # and far inside it
+    hi, lo = run(a, out="dd")
+    assert abs((hi + lo) - want) <= 1e-12 * abs(want)
+
+
+def test_b16x48_full_size_floating_point():
+    rec = golden()["b16x48"]
+    b = workloads.config_matrix("b16x48")
+    want = ref_value(rec)
+    got = run(b.astype(np.float64))
+    assert abs(got - want) <= 1e-12 * want, (got, want)
+
+
+def test_square_matches_glynn_and_limits():
+    import paper_2510_03421_amd as pg
+    a = workloads.uniform(14, 14, 9301)
+    g = pg.glynn(dev(a)).value()
+    e = run(a)
+    assert abs(g - e) <= 1e-13 * oracle.per_laplace(np.abs(a)).hi
+    assert run(np.zeros((0, 5))) == 1.0
+    with pytest.raises(pg.PermError) as ei:
+        run(np.ones((33, 40)))
+    assert ei.value.status == -2
+    with pytest.raises(pg.PermError) as ei:
+        run(np.ones((3, 49)))
+    assert ei.value.status == -2
+    with pytest.raises(pg.PermError) as ei:
+        pg.glynn_esym(dev(np.ones((3, 5), dtype=np.uint8)))     # default output: exact int128
+    assert ei.value.status == -5
+    assert pg.glynn_esym(dev(np.ones((3, 5), dtype=np.uint8)), out="f64").value() == 60.0
