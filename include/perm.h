@@ -95,7 +95,8 @@ typedef enum perm_out {
 typedef enum perm_algo {
   PERM_ALGO_COMBINATORIC = 0,
   PERM_ALGO_RYSER = 1,
-  PERM_ALGO_GLYNN = 2
+  PERM_ALGO_GLYNN = 2,
+  PERM_ALGO_GLYNN_ESYM = 3 /* perm_glynn_esym; reported by perm_auto only */
 } perm_algo;
 
 /* Flags (bitwise or). */
@@ -160,7 +161,10 @@ int perm_combinatoric(int m, int n, perm_dtype dt, const void *dA, int64_t lda, 
  * (perm_selector_load), else with the threshold table modelled on the
  * paper's Alg. 5 (App. B), and runs the first one; if that one refuses the
  * input with PERM_E_TOO_LARGE or PERM_E_OVERFLOW (e.g. Glynn's integer sum
- * carries an extra factor 2^(n-1) (n-m)!) the next one is tried.  The value
+ * carries an extra factor 2^(n-1) (n-m)!) the next one is tried.  For m < n
+ * with a floating-point output, perm_glynn_esym runs instead when its
+ * operation count, 2^(m-1) n (min(m, 32) + 1), is below half that of the
+ * first choice (terms times 2n for Glynn, 2m for Ryser, m for the definition).  The value
  * does not depend on the choice beyond rounding; integer outputs are
  * identical.  *chosen (may be NULL) receives the algorithm that ran.
  * density < 0 means "unknown" (treated as 1).  Returns the last refusal if
@@ -229,7 +233,8 @@ int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const in
  * weights stay loaded). */
 int perm_selector_load(const char *path);
 
-/* The algorithm perm_auto would try first, without running anything, for
+/* The selector's first choice among the three algorithms of Sec. 1.2 (the
+ * e_m override of perm_auto is not applied), without running anything, for
  * the default output type of dt (PERM_I64 / PERM_B8: exact integers).
  * *source (may be NULL) receives 1 if the network decided, 0 for the table.
  * PERM_E_TOO_LARGE if no algorithm admits the shape. */

@@ -25,7 +25,7 @@ __all__ = ["glynn", "glynn_esym", "ryser", "combinatoric", "auto", "value", "Per
            "profile_enable", "profile_last_ms"]
 
 ALGORITHMS = {C.PERM_ALGO_COMBINATORIC: "combinatoric", C.PERM_ALGO_RYSER: "ryser",
-              C.PERM_ALGO_GLYNN: "glynn"}
+              C.PERM_ALGO_GLYNN: "glynn", C.PERM_ALGO_GLYNN_ESYM: "glynn_esym"}
 _ALGO_ID = {v: k for k, v in ALGORITHMS.items()}
 
 _DT = {torch.float64: C.PERM_F64, torch.complex128: C.PERM_C128, torch.int64: C.PERM_I64,

@@ -25,7 +25,7 @@ PERM_OK, PERM_E_INVALID, PERM_E_TOO_LARGE, PERM_E_OVERFLOW, PERM_E_HIP, PERM_E_U
 PERM_F64, PERM_C128, PERM_I64, PERM_B8 = 0, 1, 2, 3
 PERM_OUT_F64, PERM_OUT_C128, PERM_OUT_I64, PERM_OUT_I128, PERM_OUT_DD, PERM_OUT_CDD = \
     0, 1, 2, 3, 4, 5
-PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN = 0, 1, 2
+PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN, PERM_ALGO_GLYNN_ESYM = 0, 1, 2, 3
 PERM_FLAG_WRAP = 0x1
 
 _i32, _i64, _u32, _p, _d = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, \

@@ -103,6 +103,18 @@ int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out
   int src = 0;
   const int cnt = rank_algorithms(M, N, dt, density, algo_mask(M, N, kind), order, &src);
   if (cnt == 0) return PERM_E_TOO_LARGE;
+  // the e_m form for rectangular floating-point problems when it needs well
+  // under the operations of the selector's first choice
+  if (M > 0 && M < N && kind != ENGINE_INT && M <= ESYM_MAX_M && N <= 48) {
+    const double lg_esym = (double)(M - 1) + std::log2((double)N * (std::min(M, ESYM_MAX_M) + 1));
+    const perm_algo a = order[0];
+    const double per_term = a == PERM_ALGO_GLYNN ? 2.0 * N : (a == PERM_ALGO_RYSER ? 2.0 * M : M);
+    if (lg_esym + 1.0 < log2_algo_terms(a, M, N) + std::log2(per_term)) {
+      rc = perm_glynn_esym(m, n, dt, dA, lda, ot, dOut, flags, stream);
+      if (rc == PERM_OK && chosen) *chosen = PERM_ALGO_GLYNN_ESYM;
+      if (rc != PERM_E_TOO_LARGE) return rc;
+    }
+  }
   // in predicted order; an algorithm that refuses the input (size limit, or
   // an integer bound that only it cannot meet, such as Glynn's extra factor
   // 2^(n-1) (n-m)!) passes to the next one

@@ -90,7 +90,7 @@ unsigned algo_mask(int M, int N, int kind) {
 }
 
 // log2 of the number of terms each algorithm sums (its cost up to a factor)
-static double log2_terms(perm_algo a, int M, int N) {
+double log2_algo_terms(perm_algo a, int M, int N) {
   switch (a) {
     case PERM_ALGO_COMBINATORIC: {
       double l = 0.0;
@@ -124,7 +124,7 @@ int rank_algorithms(int M, int N, perm_dtype dt, double density, unsigned mask,
       src = 1;
     } else {
       const perm_algo c = table_choice(g_net.has_table ? g_net.table : default_table(), M, N);
-      for (int a = 0; a < 3; ++a) key[a] = log2_terms((perm_algo)a, M, N);
+      for (int a = 0; a < 3; ++a) key[a] = log2_algo_terms((perm_algo)a, M, N);
       key[c] = -1e300;  // the table's choice first
     }
   }

@@ -25,6 +25,11 @@ struct ThresholdTable {
 const ThresholdTable &default_table();
 perm_algo table_choice(const ThresholdTable &t, int M, int N);
 
+// log2 of the number of terms algorithm a sums on the logical M x N shape:
+// injective maps, column subsets (square 2^N, by size sum_{s<=M} C(N, s)),
+// or Glynn's 2^(N-1) sign vectors.
+double log2_algo_terms(perm_algo a, int M, int N);
+
 // Algorithms whose size limits admit the logical M x N shape (M <= N) for an
 // engine kind: bit a set <=> perm_algo a can run it.
 unsigned algo_mask(int M, int N, int kind);

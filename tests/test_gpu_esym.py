@@ -105,3 +105,20 @@ def test_square_matches_glynn_and_limits():
         pg.glynn_esym(dev(np.ones((3, 5), dtype=np.uint8)))     # default output: exact int128
     assert ei.value.status == -5
     assert pg.glynn_esym(dev(np.ones((3, 5), dtype=np.uint8)), out="f64").value() == 60.0
+
+
+def test_auto_uses_the_e_m_form_when_it_needs_far_fewer_operations():
+    import paper_2510_03421_amd as pg
+    rec = golden()["u20x40"]
+    r = pg.auto(dev(workloads.config_matrix("u20x40")))
+    assert pg.ALGORITHMS[r.algo] == "glynn_esym"
+    assert abs(r.value() - ref_value(rec)) <= 1e-12 * abs(ref_value(rec))
+    # nearly square: Glynn stays cheaper
+    a = workloads.uniform(14, 15, 9401)
+    r = pg.auto(dev(a))
+    assert pg.ALGORITHMS[r.algo] != "glynn_esym"
+    # exact integer output: never the floating-point e_m form
+    b = (np.random.default_rng(5).random((6, 20)) < 0.5).astype(np.uint8)
+    r = pg.auto(dev(b))
+    assert pg.ALGORITHMS[r.algo] != "glynn_esym"
+    assert r.value() == oracle.per_laplace(b.astype(np.int64))
