@@ -95,7 +95,8 @@ def suite(args):
             ("u32", "glynn", None), ("u32", "ryser", None), ("c32", "glynn", None),
             ("b28", "ryser", "i128"), ("b28", "glynn", "i128"), ("b30", "ryser", "i128"),
             ("u20x40", "ryser", None), ("u20x40", "glynn", None), ("u20x40", "glynn_esym", None),
-            ("b16x48", "ryser", "i128"), ("b16x48", "glynn_esym", "f64"), ("u36", "glynn", "dd")]
+            ("b16x48", "ryser", "i128"), ("b16x48", "glynn_esym", "i128"),
+            ("b16x48", "glynn_esym", "f64"), ("u36", "glynn", "dd")]
     fn = {"glynn": pg.glynn, "ryser": pg.ryser, "combinatoric": pg.combinatoric,
           "glynn_esym": pg.glynn_esym}
     pg.profile_enable(True)

@@ -137,8 +137,10 @@ int perm_glynn(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_ou
  * with e_m the m-th elementary symmetric polynomial of c_1..c_n (expanding
  * e_m into row choices, the sign sum keeps the products that use every row
  * once).  Cost 2^(m-1) terms of O(n min(m, 32)) instead of Glynn's 2^(n-1)
- * terms for m < n.  Floating-point outputs only (PERM_E_UNSUPPORTED for
- * PERM_OUT_I64 / PERM_OUT_I128).  Limits: min(m, n) <= 32, max(m, n) <= 48. */
+ * terms for m < n.  Integer outputs are exact (the degrees are kept modulo
+ * 2^128, with the overflow pre-check of the integer paths: every column
+ * absolute sum below 2^53 and |per| 2^(m-1) below 2^127, unless
+ * PERM_FLAG_WRAP).  Limits: min(m, n) <= 32, max(m, n) <= 48. */
 int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                     void *dOut, uint32_t flags, void *stream);
 
@@ -161,8 +163,8 @@ int perm_combinatoric(int m, int n, perm_dtype dt, const void *dA, int64_t lda, 
  * (perm_selector_load), else with the threshold table modelled on the
  * paper's Alg. 5 (App. B), and runs the first one; if that one refuses the
  * input with PERM_E_TOO_LARGE or PERM_E_OVERFLOW (e.g. Glynn's integer sum
- * carries an extra factor 2^(n-1) (n-m)!) the next one is tried.  For m < n
- * with a floating-point output, perm_glynn_esym runs instead when its
+ * carries an extra factor 2^(n-1) (n-m)!) the next one is tried.  For m < n,
+ * perm_glynn_esym runs instead (if it accepts the input) when its
  * operation count, 2^(m-1) n (min(m, 32) + 1), is below half that of the
  * first choice (terms times 2n for Glynn, 2m for Ryser, m for the definition).  The value
  * does not depend on the choice beyond rounding; integer outputs are

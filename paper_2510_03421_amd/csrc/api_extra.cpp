@@ -105,14 +105,14 @@ int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out
   if (cnt == 0) return PERM_E_TOO_LARGE;
   // the e_m form for rectangular floating-point problems when it needs well
   // under the operations of the selector's first choice
-  if (M > 0 && M < N && kind != ENGINE_INT && M <= ESYM_MAX_M && N <= 48) {
+  if (M > 0 && M < N && M <= ESYM_MAX_M && N <= 48) {
     const double lg_esym = (double)(M - 1) + std::log2((double)N * (std::min(M, ESYM_MAX_M) + 1));
     const perm_algo a = order[0];
     const double per_term = a == PERM_ALGO_GLYNN ? 2.0 * N : (a == PERM_ALGO_RYSER ? 2.0 * M : M);
     if (lg_esym + 1.0 < log2_algo_terms(a, M, N) + std::log2(per_term)) {
       rc = perm_glynn_esym(m, n, dt, dA, lda, ot, dOut, flags, stream);
       if (rc == PERM_OK && chosen) *chosen = PERM_ALGO_GLYNN_ESYM;
-      if (rc != PERM_E_TOO_LARGE) return rc;
+      if (rc != PERM_E_TOO_LARGE && rc != PERM_E_OVERFLOW) return rc;
     }
   }
   // in predicted order; an algorithm that refuses the input (size limit, or

@@ -182,7 +182,7 @@ static int read_abs_sums(int M, int N, perm_dtype dt, const void *dA, int64_t ld
 }
 
 // Fills `pl` and checks overflow for an integer run of `algo` (0 Glynn,
-// 1 Ryser square/rect) on the logical M x N matrix.
+// 1 Ryser square/rect, 2 the e_m form) on the logical M x N matrix.
 int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
                  perm_out ot, uint32_t flags, hipStream_t s, int &pl) {
   const bool wrap = (flags & PERM_FLAG_WRAP) != 0;
@@ -193,13 +193,16 @@ int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t 
   } else {
     int rc = read_abs_sums(M, N, dt, dA, lda, tr, 0, rows, s);
     if (rc) return rc;
-    if (algo == 0) {
+    if (algo == 0 || algo == 2) {
       rc = read_abs_sums(M, N, dt, dA, lda, tr, 1, cols, s);
       if (rc) return rc;
-      for (auto &c : cols) c = (c > ~0ull - (uint64_t)N) ? ~0ull : c + (uint64_t)(N - M);
+      if (algo == 0)  // the padding rows of ones
+        for (auto &c : cols) c = (c > ~0ull - (uint64_t)N) ? ~0ull : c + (uint64_t)(N - M);
     }
   }
-  pl = product_levels(algo == 0 ? cols : rows);
+  // Glynn and Ryser form binary64 chunk products; the e_m form only needs
+  // every column sum exact in binary64 (product_levels < 0 iff one is not)
+  pl = product_levels(algo == 1 ? rows : cols);
   if (pl < 0) return PERM_E_OVERFLOW;
   if (wrap) return PERM_OK;
   // log2 of an upper bound on |per(A)| <= per(|A|):
@@ -246,6 +249,9 @@ int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t 
     // the Glynn sum itself is 2^(N-1) (N-M)! per(A)
     double lx = lg + (double)(N - 1) + std::lgamma((double)(N - M) + 1.0) / std::log(2.0);
     if (lx >= 127.0) return PERM_E_OVERFLOW;
+  } else if (algo == 2) {
+    // the e_m sum is 2^(M-1) per(A)
+    if (lg + (double)(M - 1) >= 127.0) return PERM_E_OVERFLOW;
   }
   return PERM_OK;
 }
@@ -359,11 +365,17 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
 // the e_m form of the rectangular Glynn sum                          //
 // ------------------------------------------------------------------ //
 int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
-             void *dOut, hipStream_t s, int kind) {
-  if (kind == ENGINE_INT) return PERM_E_UNSUPPORTED;
+             void *dOut, uint32_t flags, hipStream_t s, int kind) {
   if (M > ESYM_MAX_M || N > 48) return PERM_E_TOO_LARGE;
+  if (kind == ENGINE_INT) {
+    int pl = 0;
+    int rc = int_precheck(2, M, N, dt, dA, lda, tr, ot, flags, s, pl);
+    if (rc) return rc;
+  }
   const int nv = N, nbits = M - 1;
-  const int bpc = kind == ENGINE_CPLX ? esym_blocks_per_cu_cplx(nv) : esym_blocks_per_cu_real(nv);
+  const int bpc = kind == ENGINE_CPLX ? esym_blocks_per_cu_cplx(nv)
+                  : kind == ENGINE_INT ? esym_blocks_per_cu_int(nv)
+                                       : esym_blocks_per_cu_real(nv);
   GrayPlan plan;
   int rc = plan_gray_bpc(bpc, nbits, plan);
   if (rc) return rc;
@@ -397,8 +409,9 @@ int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, p
     w.blocks_per_lane = bpl_run;
     w.m = M;
     profile_begin(s);
-    e = kind == ENGINE_CPLX ? launch_esym_cplx(w, plan.grid, plan.block, part, s)
-                            : launch_esym_real(w, plan.grid, plan.block, part, s);
+    e = kind == ENGINE_CPLX  ? launch_esym_cplx(w, plan.grid, plan.block, part, s)
+        : kind == ENGINE_INT ? launch_esym_int(w, plan.grid, plan.block, part, s)
+                             : launch_esym_real(w, plan.grid, plan.block, part, s);
     profile_end(s);
   }
   if (e == hipSuccess) {
@@ -465,7 +478,6 @@ int perm_glynn(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_ou
 
 int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                     void *dOut, uint32_t flags, void *stream) {
-  (void)flags;
   int kind = 0;
   int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
   if (rc) return rc;
@@ -473,7 +485,7 @@ int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, pe
   const int tr = m > n;
   const int M = std::min(m, n), N = std::max(m, n);
   if (M == 0) return launch_write_one(ot, dOut, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
-  return run_esym(M, N, dt, dA, lda, tr, ot, dOut, s, kind);
+  return run_esym(M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind);
 }
 
 int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,

@@ -1,6 +1,6 @@
 // e_m form of the rectangular permanent: complex kind, vector lengths 25..48.
 #include "internal.h"
-#define ESYM_CPLX 1
+#define ESYM_KIND 1
 #define ESYM_NV_LO 25
 #define ESYM_NV_HI 48
 #define ESYM_OCC_NAME esym_occ_cplx_b

@@ -81,6 +81,23 @@ hipError_t esym_launch_real_b(const GrayWalk &w, int grid, int block, void *part
 hipError_t esym_launch_cplx_a(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
 hipError_t esym_launch_cplx_b(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
 
+int esym_occ_int_a(int nv);
+int esym_occ_int_b(int nv);
+hipError_t esym_launch_int_a(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+hipError_t esym_launch_int_b(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+
+int esym_blocks_per_cu_int(int nv) {
+  if (nv >= 1 && nv <= 24) return esym_occ_int_a(nv);
+  if (nv >= 25 && nv <= 48) return esym_occ_int_b(nv);
+  return 0;
+}
+hipError_t launch_esym_int(const GrayWalk &w, int grid, int block, void *partials,
+                           hipStream_t s) {
+  if (w.nv >= 1 && w.nv <= 24) return esym_launch_int_a(w, grid, block, partials, s);
+  if (w.nv >= 25 && w.nv <= 48) return esym_launch_int_b(w, grid, block, partials, s);
+  return hipErrorInvalidValue;
+}
+
 int esym_blocks_per_cu_real(int nv) {
   if (nv >= 1 && nv <= 24) return esym_occ_real_a(nv);
   if (nv >= 25 && nv <= 48) return esym_occ_real_b(nv);

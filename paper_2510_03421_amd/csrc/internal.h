@@ -137,14 +137,18 @@ int gray_engine_blocks_per_cu_int(int nv);
 // The e_m form of the rectangular Glynn sum (esym.inc): the walk over the
 // signs of rows 1..m-1 with the n column sums as its vector (w.nv = n,
 // w.nbits = m-1, w.m = m <= ESYM_MAX_M); each term is +-e_m(v).  Partials as
-// the real / complex engine.
+// the real / complex / integer engine (the integer kind needs every column
+// sum below 2^53 and keeps e_m modulo 2^128).
 #define ESYM_MAX_M 32
 hipError_t launch_esym_real(const GrayWalk &w, int grid, int block, void *partials,
                             hipStream_t s);
 hipError_t launch_esym_cplx(const GrayWalk &w, int grid, int block, void *partials,
                             hipStream_t s);
+hipError_t launch_esym_int(const GrayWalk &w, int grid, int block, void *partials,
+                           hipStream_t s);
 int esym_blocks_per_cu_real(int nv);
 int esym_blocks_per_cu_cplx(int nv);
+int esym_blocks_per_cu_int(int nv);
 
 // Single-workgroup deterministic reduction of `count` partials, scaling, and
 // the typed write of the result.

@@ -45,7 +45,7 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
 int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
                      perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
 int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
-             void *dOut, hipStream_t s, int kind);
+             void *dOut, uint32_t flags, hipStream_t s, int kind);
 int run_ryser_rect(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
                    void *dOut, uint32_t flags, hipStream_t s, int kind);
 

@@ -1,7 +1,7 @@
 """The e_m form of the rectangular Glynn sum (perm_glynn_esym) against the
-oracle: exact on integer-valued inputs that stay below 2^53, within the
-rounding bound of the formula on real and complex inputs, and at full size
-on the 20x40 and 16x48 workloads."""
+oracle: bit-exact for integer outputs and for floating-point results on
+integer-valued inputs below 2^53, within the rounding bound of the formula on
+real and complex inputs, and at full size on the 20x40 and 16x48 workloads."""
 import itertools
 import math
 
@@ -50,6 +50,9 @@ def test_small_integer_valued_exact(m, n):
     assert run(np.ascontiguousarray(a.T).astype(np.float64)) == float(want)   # m > n
     z = a.astype(np.complex128) * (1 - 2j)
     assert run(z) == complex(want * (1 - 2j) ** m)
+    assert run(a.astype(np.int64)) == want                       # exact int128 output
+    b = (rng.random((m, n)) < 0.6).astype(np.uint8)
+    assert run(b) == oracle.per_brute(b.astype(np.int64))
 
 
 @pytest.mark.parametrize("m,n,seed", [(3, 11, 1), (6, 14, 2), (9, 20, 3), (12, 24, 4), (12, 12, 5),
@@ -80,12 +83,27 @@ def test_u20x40_full_size():
     assert abs((hi + lo) - want) <= 1e-12 * abs(want)
 
 
-def test_b16x48_full_size_floating_point():
+def test_b16x48_full_size():
     rec = golden()["b16x48"]
     b = workloads.config_matrix("b16x48")
     want = ref_value(rec)
+    assert run(b) == want                                  # bit-exact, int128
     got = run(b.astype(np.float64))
     assert abs(got - want) <= 1e-12 * want, (got, want)
+
+
+def test_integer_overflow_precheck_and_wrap():
+    import paper_2510_03421_amd as pg
+    # 20 x 30 ones: per = 30!/10! ~ 2^86; the e_m sum 2^19 per fits int128
+    assert run(np.ones((20, 30), dtype=np.uint8)) == math.factorial(30) // math.factorial(10)
+    # 32 x 40 ones: per = 40!/8! ~ 2^144 does not fit: refused ...
+    big = np.ones((32, 40), dtype=np.uint8)
+    with pytest.raises(pg.PermError) as ei:
+        run(big)
+    assert ei.value.status == -3
+    # ... and with PERM_FLAG_WRAP exact modulo 2^(128 - 31)
+    got = pg.glynn_esym(dev(big), flags=pg._capi.PERM_FLAG_WRAP).value()
+    assert (got - math.factorial(40) // math.factorial(8)) % 2 ** 97 == 0
 
 
 def test_square_matches_glynn_and_limits():
@@ -101,9 +119,7 @@ def test_square_matches_glynn_and_limits():
     with pytest.raises(pg.PermError) as ei:
         run(np.ones((3, 49)))
     assert ei.value.status == -2
-    with pytest.raises(pg.PermError) as ei:
-        pg.glynn_esym(dev(np.ones((3, 5), dtype=np.uint8)))     # default output: exact int128
-    assert ei.value.status == -5
+    assert pg.glynn_esym(dev(np.ones((3, 5), dtype=np.uint8))).value() == 60
     assert pg.glynn_esym(dev(np.ones((3, 5), dtype=np.uint8)), out="f64").value() == 60.0
 
 
@@ -117,8 +133,8 @@ def test_auto_uses_the_e_m_form_when_it_needs_far_fewer_operations():
     a = workloads.uniform(14, 15, 9401)
     r = pg.auto(dev(a))
     assert pg.ALGORITHMS[r.algo] != "glynn_esym"
-    # exact integer output: never the floating-point e_m form
+    # exact integer output, through the integer kind of the e_m form
     b = (np.random.default_rng(5).random((6, 20)) < 0.5).astype(np.uint8)
     r = pg.auto(dev(b))
-    assert pg.ALGORITHMS[r.algo] != "glynn_esym"
+    assert pg.ALGORITHMS[r.algo] == "glynn_esym"
     assert r.value() == oracle.per_laplace(b.astype(np.int64))
