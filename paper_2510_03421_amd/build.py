@@ -59,13 +59,23 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+def _includes(path: str, seen: set) -> set:
+    """Local files `path` includes, recursively (quoted #include only)."""
+    import re
+    for inc in re.findall(r'^\s*#\s*include\s+"([^"]+)"', open(path).read(), flags=re.M):
+        dep = os.path.normpath(os.path.join(os.path.dirname(path), inc))
+        if os.path.exists(dep) and dep not in seen:
+            seen.add(dep)
+            _includes(dep, seen)
+    return seen
+
+
 def _stale(src: str) -> bool:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
     if not os.path.exists(obj):
         return True
-    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, f) for f in os.listdir(CSRC)
-                                        if f.endswith((".h", ".inc"))]
-    deps.append(os.path.join(ROOT, "include", "perm.h"))
+    path = os.path.join(CSRC, src)
+    deps = [path] + sorted(_includes(path, set()))
     return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
 
 
