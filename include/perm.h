@@ -100,6 +100,10 @@ typedef enum perm_algo {
 } perm_algo;
 
 /* Flags (bitwise or). */
+#define PERM_FLAG_PAD_ONES 0x2u /* perm_glynn, floating point, m < n: pad with rows of
+                                   ones exactly as Eq. glynn_filled_matrix (by default
+                                   the padding value is a power of two scaled to the
+                                   data, see perm_glynn) */
 #define PERM_FLAG_WRAP 0x1u /* integer outputs: skip the overflow pre-check and
                                return the exact value modulo 2^64 / 2^128 (for
                                Glynn: modulo 2^(128-(n-1)-v), v the power of two
@@ -124,7 +128,13 @@ int perm_profile_last(double *ms);
  *   per(A) = 2^-(n-1) sum_{delta in {+-1}^n, delta_1=+1} (prod delta) prod_j sum_i delta_i a_ij
  * summed in reflected Gray-code order; for m < n the matrix is padded with
  * n - m rows of ones and the sum divided by (n-m)! (Eq. glynn_filled_matrix,
- * Eq. glynn_rectangle).  Cost 2^(n-1) terms of O(n), n = max(m, n).
+ * Eq. glynn_rectangle).  With floating-point outputs the padding rows hold
+ * c = 2^e instead, e = round(log2(rms(A) sqrt(m) / (n-m))) computed on the
+ * device, and the sum is divided by (n-m)! c^(n-m) (exact rescaling:
+ * per([A; cJ]) = c^(n-m) per([A; J])); with rows of ones the padding
+ * dominates the column sums and the sum loses most of its digits.
+ * PERM_FLAG_PAD_ONES keeps the value 1.  Integer outputs always pad with
+ * ones.  Cost 2^(n-1) terms of O(n), n = max(m, n).
  * Limit: n <= 48 for floating-point outputs, n <= 40 for integer outputs. */
 int perm_glynn(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                void *dOut, uint32_t flags, void *stream);

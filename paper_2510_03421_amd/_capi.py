@@ -27,6 +27,7 @@ PERM_OUT_F64, PERM_OUT_C128, PERM_OUT_I64, PERM_OUT_I128, PERM_OUT_DD, PERM_OUT_
     0, 1, 2, 3, 4, 5
 PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN, PERM_ALGO_GLYNN_ESYM = 0, 1, 2, 3
 PERM_FLAG_WRAP = 0x1
+PERM_FLAG_PAD_ONES = 0x2
 
 _i32, _i64, _u32, _p, _d = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, \
     ctypes.c_double

@@ -330,7 +330,15 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
   double *tbl = (double *)scratch;
   double *base = tbl + tbl_n;
   double *part = base + base_n;
-  hipError_t e = launch_stage_gray(algo, M, N, dt, dA, lda, tr, tbl, base, C == 2, s);
+  // floating-point rectangular Glynn: padding rows of 2^e (chosen on the
+  // device from the data) instead of ones, unless the caller asks for ones
+  int *pad_exp = nullptr;
+  hipError_t e = hipSuccess;
+  if (algo == 0 && M < N && kind != ENGINE_INT && !(flags & PERM_FLAG_PAD_ONES)) {
+    pad_exp = (int *)(part + part_n);
+    e = launch_pad_scale(M, N, dt, dA, lda, tr, pad_exp, s);
+  }
+  if (e == hipSuccess) e = launch_stage_gray(algo, M, N, dt, dA, lda, tr, tbl, base, C == 2, s, pad_exp);
   if (e == hipSuccess) {
     GrayWalk w;
     w.tbl = tbl;
@@ -354,6 +362,7 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     f.m = M;
     f.n = N;
     f.ot = ot;
+    f.pad_exp = pad_exp;
     e = launch_finish(kind, part, plan.grid, f, dOut, s);
   }
   hipError_t e2 = hipFreeAsync(scratch, s);

@@ -110,6 +110,7 @@ struct Finish {
   int mode;       // FinishMode
   int m, n;       // logical shape after orientation (m <= n)
   perm_out ot;
+  const int *pad_exp = nullptr;  // FINISH_GLYNN, floating point: padding rows held 2^(*pad_exp)
 };
 
 // ---- launchers (each returns a hipError_t) ----
@@ -118,7 +119,11 @@ struct Finish {
 // rows only (algo 2, for the e_m form); converts the input dtype; `tr` reads
 // A^T.
 hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
-                             int tr, double *tbl, double *base, int cplx, hipStream_t s);
+                             int tr, double *tbl, double *base, int cplx, hipStream_t s,
+                             const int *pad_exp = nullptr);
+// The exponent of the floating-point Glynn padding value (device int *e).
+hipError_t launch_pad_scale(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                            int *e, hipStream_t s);
 
 // Engine: one partial per workgroup into `partials` (real: 2 doubles,
 // complex: 4 doubles, int: 2 uint64).  The walk's vector length w.nv must be

@@ -23,13 +23,49 @@ __device__ __forceinline__ void read_entry(perm_dtype dt, const void *dA, int64_
   }
 }
 
-// algo 0 (Glynn): NV = n, nbits = n-1, padded matrix a' (rows m..n-1 are ones),
+// Exponent e of the padding value 2^e of the floating-point Glynn sum on an
+// m x n matrix (m < n): the nearest power of two to rms(A) sqrt(m) / (n - m),
+// which keeps the padding rows' share of the column sums comparable to the
+// data's (with 1 the padding dominates and the sum cancels badly).  One
+// workgroup; the result goes to *e (0 for a zero matrix).
+__global__ __launch_bounds__(kReduceThreads) void pad_scale_kernel(int m, int n, perm_dtype dt,
+                                                                  const void *dA, int64_t lda,
+                                                                  int tr, int *e) {
+  __shared__ double sh[kReduceThreads];
+  double acc = 0.0;
+  for (int idx = threadIdx.x; idx < m * n; idx += blockDim.x) {
+    double re, im;
+    read_entry(dt, dA, lda, tr, idx / n, idx % n, re, im);
+    acc += re * re + im * im;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kReduceThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double ms = sh[0] / ((double)m * (double)n);
+    int x = 0;
+    if (ms > 0.0 && n > m) {
+      const double c = __builtin_sqrt(ms) * __builtin_sqrt((double)m) / (double)(n - m);
+      x = (int)rint(log2(c));
+      x = x < -200 ? -200 : (x > 200 ? 200 : x);
+    }
+    *e = x;
+  }
+}
+
+// algo 0 (Glynn): NV = n, nbits = n-1, padded matrix a' (rows m..n-1 hold the
+//   padding value: 2^(*pad_exp), or 1 when pad_exp is null),
 //   base_j = sum_i a'_ij, U[q]_j = -2 a'_{q+1, j}.
 // algo 1 (square Ryser): NV = m, nbits = n, base = 0, U[q]_i = a_{i, q}.
 // algo 2 (signs of the m rows only, no padding): NV = n, nbits = m-1,
 //   base_j = sum_{i<m} a_ij, U[q]_j = -2 a_{q+1, j}.
 __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const void *dA,
-                                  int64_t lda, int tr, double *tbl, double *base, int C) {
+                                  int64_t lda, int tr, double *tbl, double *base, int C,
+                                  const int *pad_exp) {
+  const double pad = pad_exp ? __builtin_ldexp(1.0, *pad_exp) : 1.0;
   const int nv = algo == 1 ? m : n;
   const int nbits = algo == 0 ? n - 1 : (algo == 1 ? n : m - 1);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -40,7 +76,7 @@ __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const v
       if (q + 1 < m) {
         read_entry(dt, dA, lda, tr, q + 1, j, re, im);
       } else {
-        re = 1.0;
+        re = pad;
         im = 0.0;
       }
       re *= -2.0;
@@ -61,7 +97,7 @@ __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const v
     double sr = 0.0, si = 0.0;
     if (algo != 1) {
       for (int i = 0; i < (algo == 0 ? n : m); ++i) {
-        double re = 1.0, im = 0.0;
+        double re = pad, im = 0.0;
         if (i < m) read_entry(dt, dA, lda, tr, i, idx, re, im);
         sr += re;
         si += im;
@@ -171,7 +207,9 @@ __global__ __launch_bounds__(kReduceThreads) void finish_kernel(int kind, const 
   if (t == 0) {
     double rh = sh[0][0], rl = sh[0][1], ih = sh[0][2], il = sh[0][3];
     if (f.mode == FINISH_GLYNN) {
-      const double sc = __builtin_ldexp(1.0, -(f.n - 1));
+      // 2^-(n-1), and 2^(-e (n-m)) for padding rows of 2^e: exact scalings
+      const int pe = f.pad_exp ? *f.pad_exp : 0;
+      const double sc = __builtin_ldexp(1.0, -(f.n - 1) - pe * (f.n - f.m));
       rh *= sc; rl *= sc; ih *= sc; il *= sc;            // exact
       for (int q = 2; q <= f.n - f.m; ++q) {
         dd_div_d(rh, rl, (double)q);
@@ -273,15 +311,23 @@ __global__ void stage_rect_kernel(int m, int n, int l, perm_dtype dt, const void
 
 }  // namespace
 
+hipError_t launch_pad_scale(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                            int *e, hipStream_t s) {
+  hipLaunchKernelGGL(pad_scale_kernel, dim3(1), dim3(kReduceThreads), 0, s, m, n, dt, dA, lda, tr,
+                     e);
+  return hipGetLastError();
+}
+
 hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
-                             int tr, double *tbl, double *base, int cplx, hipStream_t s) {
+                             int tr, double *tbl, double *base, int cplx, hipStream_t s,
+                             const int *pad_exp) {
   const int nv = algo == 1 ? m : n;
   const int nbits = algo == 0 ? n - 1 : (algo == 1 ? n : m - 1);
   int work = nbits * nv > nv ? nbits * nv : nv;
   if (work < 1) work = 1;
   const int threads = 256, blocks = (work + threads - 1) / threads;
   hipLaunchKernelGGL(stage_gray_kernel, dim3(blocks), dim3(threads), 0, s, algo, m, n, dt, dA, lda,
-                     tr, tbl, base, cplx ? 2 : 1);
+                     tr, tbl, base, cplx ? 2 : 1, pad_exp);
   return hipGetLastError();
 }
 

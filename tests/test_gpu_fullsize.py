@@ -118,12 +118,16 @@ def test_u20x40_rectangular():
     # by-size Ryser weights reach C(39, 19) ~ 7e10 with alternating signs:
     # measured relative error ~1e-7, far inside the per(|A|) criterion
     rel_ryser = fp_check(run_algo("ryser", a), r, 1e-5)
-    # the padded Glynn form (Eq. glynn_rectangle) is ill-conditioned for
-    # m << n: it meets the per(|A|) criterion but keeps few correct digits
-    g = run_algo("glynn", a)
-    err = abs(g - ref_value(r))
-    assert err <= CRIT * abs_ref(r)
-    assert rel_ryser < 1e-5
+    # the padded Glynn form (Eq. glynn_rectangle) with rows of ones is
+    # ill-conditioned for m << n: it meets the per(|A|) criterion but keeps few
+    # correct digits ...
+    import paper_2510_03421_amd as pg
+    g = run_algo("glynn", a, flags=pg._capi.PERM_FLAG_PAD_ONES)
+    assert abs(g - ref_value(r)) <= CRIT * abs_ref(r)
+    # ... padding rows of 2^e scaled to the data (the default) keep them
+    g2 = run_algo("glynn", a)
+    rel_glynn = fp_check(g2, r, 1e-9)
+    assert rel_glynn < 1e-9 and rel_ryser < 1e-5
 
 
 def test_u36_glynn_double_double():
