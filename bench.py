@@ -4,9 +4,12 @@ uniform on [-1, 1], seed 3201) -- the hot path's headline configuration.
 One step = one perm_glynn call on a device-resident matrix: staging of the
 update table, 2^31 Gray-code terms (closed-form re-seed per lane block, one
 row update and one 32-factor product per term, compensated accumulation),
-the deterministic reduction and the final scaling.  Prints one JSON line.
+the deterministic reduction and the final scaling.  Prints one JSON line,
+which also carries the batched record (200,000 complex submatrices of a
+Haar unitary, one graph launch) and the CPU oracle baseline.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched]
+    python bench.py --suite      (every workload configuration, one line each)
 """
 from __future__ import annotations
 
@@ -143,10 +146,11 @@ def suite(args):
     batched(args)
 
 
-def batched(args, count: int = 200_000, sample: int = 20_000):
+def batched(args, count: int = 200_000, sample: int = 20_000, emit: bool = True):
     """200,000 complex128 submatrices (orders uniform in 4..20) of one seeded
     64 x 64 Haar unitary: one plan, one graph launch, against a loop of
-    single-matrix launches over the first `sample` matrices."""
+    single-matrix launches over the first `sample` matrices.  Prints the
+    record (emit) and returns it."""
     import numpy as np
     import torch
 
@@ -183,14 +187,17 @@ def batched(args, count: int = 200_000, sample: int = 20_000):
     vs = single.view(-1, 2)
     maxdiff = float((vb - vs).abs().max())
     bound = float(torch.sqrt((out.view(-1, 2) ** 2).sum(1)).max())
-    print(json.dumps({"workload": "batched_boson_200000_c128_n4..20", "count": count,
-                      "terms": terms, "graph_ms": t_batch * 1e3,
-                      "perms_per_s": count / t_batch, "terms_per_s": terms / t_batch,
-                      "single_launch_perms_per_s": 1.0 / t_single,
-                      "speedup_vs_single_launches": t_single * count / t_batch,
-                      "max_abs_diff_vs_single_on_sample": maxdiff,
-                      "max_abs_per": bound}), flush=True)
+    rec = {"workload": "batched_boson_200000_c128_n4..20", "count": count,
+           "terms": terms, "graph_ms": t_batch * 1e3,
+           "perms_per_s": count / t_batch, "terms_per_s": terms / t_batch,
+           "single_launch_perms_per_s": 1.0 / t_single, "single_launch_sample": sample,
+           "speedup_vs_single_launches": t_single * count / t_batch,
+           "max_abs_diff_vs_single_on_sample": maxdiff,
+           "max_abs_per": bound}
+    if emit:
+        print(json.dumps(rec), flush=True)
     plan.close()
+    return rec
 
 
 def main():
@@ -199,6 +206,8 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched (200,000 boson submatrices) record")
     ap.add_argument("--suite", action="store_true",
                     help="instead of the one contract line, time every workload "
                          "configuration (one JSON line each)")
@@ -302,6 +311,10 @@ def main():
         "result": result,
         "error_vs_oracle": err,
     }
+    if not args.no_batched:
+        # the metric's second part: batched permanents per second (one graph
+        # launch) against one perm_glynn call per matrix on a sample
+        line["batched"] = batched(args, sample=2_000, emit=False)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(a_host)
     print(json.dumps(line), flush=True)
