@@ -112,6 +112,14 @@ typedef enum perm_algo {
 /* Library version, PERM_VERSION. */
 int perm_version(void);
 
+/* Releases the device memory the library keeps on the current device: the
+ * cached tables of the rectangular Ryser walk (revolving-door transitions,
+ * binomials; rebuilt on next use) and the unused memory of the device's
+ * stream-ordered pool that per-call scratch came from.  Waits for the device
+ * first, so no call may be in flight on it.  Batch plans keep their own memory
+ * until perm_batch_plan_destroy. */
+int perm_workspace_release(void);
+
 /* Static description of a status code (never NULL). */
 const char *perm_status_string(int status);
 

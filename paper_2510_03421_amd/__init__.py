@@ -22,7 +22,7 @@ from ._capi import PermError
 
 __all__ = ["glynn", "glynn_esym", "ryser", "combinatoric", "auto", "value", "PermError", "BatchPlan",
            "glynn_batched", "select", "selector_load", "ALGORITHMS", "version",
-           "profile_enable", "profile_last_ms"]
+           "profile_enable", "profile_last_ms", "workspace_release"]
 
 ALGORITHMS = {C.PERM_ALGO_COMBINATORIC: "combinatoric", C.PERM_ALGO_RYSER: "ryser",
               C.PERM_ALGO_GLYNN: "glynn", C.PERM_ALGO_GLYNN_ESYM: "glynn_esym"}
@@ -40,6 +40,11 @@ _OUTBUF = {"f64": (torch.float64, 1), "c128": (torch.float64, 2), "i64": (torch.
 
 def version() -> int:
     return int(C.lib.perm_version())
+
+
+def workspace_release() -> None:
+    """Free the library's cached device tables and trim the stream-ordered pool."""
+    C.check(C.lib.perm_workspace_release(), "perm_workspace_release")
 
 
 def profile_enable(on: bool = True) -> None:

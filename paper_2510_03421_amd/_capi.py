@@ -38,6 +38,8 @@ for _name in ("perm_glynn", "perm_ryser", "perm_combinatoric", "perm_glynn_esym"
     getattr(lib, _name).restype = _i32
 lib.perm_auto.argtypes = _single + [_d, ctypes.POINTER(_i32)]
 lib.perm_auto.restype = _i32
+lib.perm_workspace_release.argtypes = []
+lib.perm_workspace_release.restype = _i32
 lib.perm_version.argtypes = []
 lib.perm_version.restype = _i32
 lib.perm_profile_enable.argtypes = [_i32]

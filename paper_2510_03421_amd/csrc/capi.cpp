@@ -445,6 +445,17 @@ extern "C" {
 
 int perm_version(void) { return PERM_VERSION; }
 
+int perm_workspace_release(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PERM_E_HIP;
+  if (hipDeviceSynchronize() != hipSuccess) return PERM_E_HIP;
+  int rc = release_rect_tables(dev);
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess || hipMemPoolTrimTo(pool, 0) != hipSuccess)
+    rc = PERM_E_HIP;
+  return rc;
+}
+
 int perm_profile_enable(int on) {
   g_profile.store(on ? 1 : 0);
   return PERM_OK;

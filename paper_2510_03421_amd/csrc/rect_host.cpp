@@ -69,10 +69,14 @@ struct DevTables {
   uint64_t *binom = nullptr;
 };
 
+std::mutex g_tables_mu;
+std::map<std::pair<int, int>, uint32_t *> g_trans_cache;
+std::map<int, uint64_t *> g_binom_cache;
+
 int device_tables(int l, DevTables &out) {
-  static std::mutex mu;
-  static std::map<std::pair<int, int>, uint32_t *> trans_cache;
-  static std::map<int, uint64_t *> binom_cache;
+  auto &mu = g_tables_mu;
+  auto &trans_cache = g_trans_cache;
+  auto &binom_cache = g_binom_cache;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return PERM_E_HIP;
   const DoorTables &t = door_tables(l);
@@ -144,6 +148,26 @@ void plan_classes(int M, int N, int l, ClassPlan &c) {
 }
 
 }  // namespace
+
+// Frees the cached device tables of `dev` (they are rebuilt on next use).
+int release_rect_tables(int dev) {
+  std::lock_guard<std::mutex> g(g_tables_mu);
+  int rc = PERM_OK;
+  for (auto it = g_trans_cache.begin(); it != g_trans_cache.end();) {
+    if (it->first.first == dev) {
+      if (hipFree(it->second) != hipSuccess) rc = PERM_E_HIP;
+      it = g_trans_cache.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  auto b = g_binom_cache.find(dev);
+  if (b != g_binom_cache.end()) {
+    if (hipFree(b->second) != hipSuccess) rc = PERM_E_HIP;
+    g_binom_cache.erase(b);
+  }
+  return rc;
+}
 
 int run_ryser_rect(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
                    void *dOut, uint32_t flags, hipStream_t s, int kind) {

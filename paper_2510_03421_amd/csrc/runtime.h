@@ -46,6 +46,7 @@ int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, i
                      perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
 int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
              void *dOut, uint32_t flags, hipStream_t s, int kind);
+int release_rect_tables(int dev);
 int run_ryser_rect(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
                    void *dOut, uint32_t flags, hipStream_t s, int kind);
 

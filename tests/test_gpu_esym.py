@@ -138,3 +138,14 @@ def test_auto_uses_the_e_m_form_when_it_needs_far_fewer_operations():
     r = pg.auto(dev(b))
     assert pg.ALGORITHMS[r.algo] == "glynn_esym"
     assert r.value() == oracle.per_laplace(b.astype(np.int64))
+
+
+def test_workspace_release_then_rectangular_ryser_again():
+    """Releasing the cached tables and the pool leaves every path working."""
+    import paper_2510_03421_amd as pg
+    b = (np.random.default_rng(8).random((6, 20)) < 0.5).astype(np.uint8)
+    want = oracle.per_laplace(b.astype(np.int64))
+    assert pg.ryser(dev(b)).value() == want
+    pg.workspace_release()
+    assert pg.ryser(dev(b)).value() == want
+    assert run(b) == want
