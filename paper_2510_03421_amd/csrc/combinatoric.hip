@@ -4,8 +4,17 @@
 // Maps are ranked in lexicographic order of (s(0), ..., s(m-1)): the rank's
 // mixed-radix digits d_i in bases n, n-1, ..., n-m+1 pick s(i) as the d_i-th
 // column not used by rows 0..i-1.  Each thread takes a contiguous range of
-// ranks; A is staged in LDS.  Real products are summed with a compensated
-// accumulator, integer products modulo 2^128.
+// ranks; it decodes its first rank once and then counts like an odometer:
+// the next rank increments the last digit and carries, and only the rows from
+// the highest changed digit on get new columns -- the next free column above
+// the old one at that digit, the lowest free column after it -- and new
+// prefix products (the same left-to-right products as a fresh evaluation).
+// The number of rows m is a template parameter (n!/(n-m)! <= 2^40 forces
+// m <= 14), so the per-row state stays in registers.  A is staged in LDS.
+// Real products are summed with a compensated accumulator, integer products
+// modulo 2^128.
+#include <utility>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -25,12 +34,13 @@ __device__ __forceinline__ int nth_unused(uint64_t used, int d) {
   }
 }
 
-template <int KIND>
-__global__ __launch_bounds__(kThreads) void combinatoric_kernel(int m, int n, perm_dtype dt,
+template <int KIND, int M>
+__global__ __launch_bounds__(kThreads) void combinatoric_kernel(int n, perm_dtype dt,
                                                                 const void *dA, int64_t lda,
                                                                 int tr, uint64_t total,
                                                                 void *partials) {
-  extern __shared__ double sa[];  // m*n (x2 for complex) entries
+  extern __shared__ double sa[];  // M*n (x2 for complex) entries
+  constexpr int m = M;
   constexpr int C = KIND == ENGINE_CPLX ? 2 : 1;
   for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
@@ -62,53 +72,86 @@ __global__ __launch_bounds__(kThreads) void combinatoric_kernel(int m, int n, pe
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t r0 = (uint64_t)(((u128)total * t) / T);
   const uint64_t r1 = (uint64_t)(((u128)total * (t + 1)) / T);
+  const uint64_t free_cols = n >= 64 ? ~0ull : ((1ull << n) - 1);
   double hi = 0.0, lo = 0.0, hi2 = 0.0, lo2 = 0.0;
   u128 acc = 0;
-  for (uint64_t r = r0; r < r1; ++r) {
-    // digits, least significant (last row) first
-    int dig[64];
-    uint64_t x = r;
-    for (int i = m - 1; i >= 0; --i) {
+  if (r0 < r1) {
+    int dig[M], col[M];
+    uint64_t used[M + 1];  // columns taken by rows 0..i-1
+    double pr[M], pi_[M];  // prefix products (real / complex)
+    u128 pint[M];          // prefix products (integer)
+    // the row-i prefix product from row i-1's and entry (i, col[i])
+    auto extend = [&](int i) {
+      const int j = col[i];
+      if constexpr (KIND == ENGINE_REAL) {
+        pr[i] = i == 0 ? sa[i * n + j] : pr[i - 1] * sa[i * n + j];
+      } else if constexpr (KIND == ENGINE_CPLX) {
+        const double ar = sa[2 * (i * n + j)], ai = sa[2 * (i * n + j) + 1];
+        if (i == 0) {
+          pr[0] = ar;
+          pi_[0] = ai;
+        } else {
+          pr[i] = pr[i - 1] * ar - pi_[i - 1] * ai;
+          pi_[i] = pr[i - 1] * ai + pi_[i - 1] * ar;
+        }
+      } else {
+        const u128 v = (u128)(i128)__double_as_longlong(sa[i * n + j]);
+        pint[i] = i == 0 ? v : pint[i - 1] * v;
+      }
+    };
+    // decode the first rank: digits, least significant (last row) first
+    uint64_t x = r0;
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
       const uint64_t base = (uint64_t)(n - i);
       dig[i] = (int)(x % base);
       x /= base;
     }
-    uint64_t used = 0;
-    if constexpr (KIND == ENGINE_REAL) {
-      double p = 1.0;
-      for (int i = 0; i < m; ++i) {
-        const int j = nth_unused(used, dig[i]);
-        used |= 1ull << j;
-        p = i == 0 ? sa[i * n + j] : p * sa[i * n + j];
+    used[0] = 0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      col[i] = nth_unused(used[i], dig[i]);
+      used[i + 1] = used[i] | (1ull << col[i]);
+      extend(i);
+    }
+    for (uint64_t r = r0;;) {
+      if constexpr (KIND == ENGINE_REAL) {
+        dd_acc(hi, lo, pr[M - 1]);
+      } else if constexpr (KIND == ENGINE_CPLX) {
+        dd_acc(hi, lo, pr[M - 1]);
+        dd_acc(hi2, lo2, pi_[M - 1]);
+      } else {
+        acc += pint[M - 1];
       }
-      dd_acc(hi, lo, p);
-    } else if constexpr (KIND == ENGINE_CPLX) {
-      double pr = 1.0, pi = 0.0;
-      for (int i = 0; i < m; ++i) {
-        const int j = nth_unused(used, dig[i]);
-        used |= 1ull << j;
-        const double ar = sa[2 * (i * n + j)], ai = sa[2 * (i * n + j) + 1];
-        if (i == 0) {
-          pr = ar;
-          pi = ai;
-        } else {
-          const double qr = pr * ar - pi * ai;
-          const double qi = pr * ai + pi * ar;
-          pr = qr;
-          pi = qi;
+      if (++r >= r1) break;
+      // odometer step: p = the highest digit that changes (r < total, so one does)
+      int p = 0;
+      bool carry = true;
+#pragma unroll
+      for (int i = M - 1; i >= 0; --i) {
+        if (carry) {
+          if (dig[i] + 1 == n - i) {
+            dig[i] = 0;
+          } else {
+            ++dig[i];
+            carry = false;
+            p = i;
+          }
         }
       }
-      dd_acc(hi, lo, pr);
-      dd_acc(hi2, lo2, pi);
-    } else {
-      u128 p = 1;
-      for (int i = 0; i < m; ++i) {
-        const int j = nth_unused(used, dig[i]);
-        used |= 1ull << j;
-        const int64_t v = __double_as_longlong(sa[i * n + j]);
-        p *= (u128)(i128)v;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        if (i >= p) {
+          // digit p moved to the next free column above its old one; every
+          // later digit restarted at 0: the lowest free column
+          const uint64_t avail = ~used[i] & free_cols;
+          const uint64_t above =
+              i == p ? (col[i] >= 63 ? 0ull : (~0ull << (col[i] + 1))) : ~0ull;
+          col[i] = __builtin_ctzll(avail & above);
+          used[i + 1] = used[i] | (1ull << col[i]);
+          extend(i);
+        }
       }
-      acc += p;
     }
   }
   // workgroup reduction -> one partial
@@ -159,26 +202,42 @@ __global__ __launch_bounds__(kThreads) void combinatoric_kernel(int m, int n, pe
   }
 }
 
+template <int KIND, int M>
+hipError_t launch_one(int n, perm_dtype dt, const void *dA, int64_t lda, int tr, uint64_t total,
+                      int grid, void *partials, hipStream_t s) {
+  const size_t lds = sizeof(double) * (size_t)M * n * (KIND == ENGINE_CPLX ? 2 : 1);
+  hipLaunchKernelGGL((combinatoric_kernel<KIND, M>), dim3(grid), dim3(kThreads), lds, s, n, dt,
+                     dA, lda, tr, total, partials);
+  return hipGetLastError();
+}
+
+template <int KIND, int... Ms>
+hipError_t launch_m(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                    uint64_t total, int grid, void *partials, hipStream_t s,
+                    std::integer_sequence<int, Ms...>) {
+  hipError_t e = hipErrorInvalidValue;
+  ((m == Ms + 1 ? (e = launch_one<KIND, Ms + 1>(n, dt, dA, lda, tr, total, grid, partials, s), 0)
+                : 0),
+   ...);
+  return e;
+}
+
 }  // namespace
 
+// m <= kCombMaxM: n!/(n-m)! >= m!, and the host limits the maps to 2^40 < 15!
 hipError_t launch_combinatoric(int kind, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
                                int tr, uint64_t total, int grid, void *partials, hipStream_t s) {
-  const size_t lds = sizeof(double) * (size_t)m * n * (kind == ENGINE_CPLX ? 2 : 1);
+  constexpr int kCombMaxM = 14;
+  if (m < 1 || m > kCombMaxM) return hipErrorInvalidValue;
+  const auto seq = std::make_integer_sequence<int, kCombMaxM>{};
   switch (kind) {
     case ENGINE_REAL:
-      hipLaunchKernelGGL(combinatoric_kernel<ENGINE_REAL>, dim3(grid), dim3(kThreads), lds, s, m,
-                         n, dt, dA, lda, tr, total, partials);
-      break;
+      return launch_m<ENGINE_REAL>(m, n, dt, dA, lda, tr, total, grid, partials, s, seq);
     case ENGINE_CPLX:
-      hipLaunchKernelGGL(combinatoric_kernel<ENGINE_CPLX>, dim3(grid), dim3(kThreads), lds, s, m,
-                         n, dt, dA, lda, tr, total, partials);
-      break;
+      return launch_m<ENGINE_CPLX>(m, n, dt, dA, lda, tr, total, grid, partials, s, seq);
     default:
-      hipLaunchKernelGGL(combinatoric_kernel<ENGINE_INT>, dim3(grid), dim3(kThreads), lds, s, m,
-                         n, dt, dA, lda, tr, total, partials);
-      break;
+      return launch_m<ENGINE_INT>(m, n, dt, dA, lda, tr, total, grid, partials, s, seq);
   }
-  return hipGetLastError();
 }
 
 }  // namespace permgpu
