@@ -1,5 +1,6 @@
 // Batched Glynn: per-matrix finishing kernel and the launch sequence (one
-// persistent kernel per matrix order, then the finish).
+// kernel per matrix order -- packed small orders or chunked persistent ones --
+// then the finish).
 #include "device_common.h"
 #include "internal.h"
 
@@ -61,7 +62,10 @@ hipError_t launch_batched(const BatchLaunch &L, hipStream_t s) {
   hipError_t e = hipSuccess;
   for (int i = 0; i < L.nbuckets && e == hipSuccess; ++i) {
     const BatchBucket &bk = L.buckets[i];
-    if (L.kind == ENGINE_CPLX)
+    if (bk.pack > 0)
+      e = L.kind == ENGINE_CPLX ? launch_batched_small_cplx(bk.n, bk, L, s)
+                                : launch_batched_small_real(bk.n, bk, L, s);
+    else if (L.kind == ENGINE_CPLX)
       e = bk.n <= 20 ? batched_launch_cplx_a(bk.n, bk, L, s) : batched_launch_cplx_b(bk.n, bk, L, s);
     else
       e = bk.n <= 20 ? batched_launch_real_a(bk.n, bk, L, s) : batched_launch_real_b(bk.n, bk, L, s);

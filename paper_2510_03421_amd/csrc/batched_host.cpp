@@ -58,6 +58,37 @@ int batch_block_log2(int nbits) {
   return std::max(0, std::min(b, cap));
 }
 
+// Orders up to this many columns run several matrices per wave.
+int pack_max_n() {
+  static const int v = [] {
+    const char *e = std::getenv("PERM_BATCH_PACK_MAX_N");
+    const int x = e ? std::atoi(e) : BATCH_PACK_MAX_N;
+    return x >= 0 && x <= BATCH_PACK_MAX_N ? x : BATCH_PACK_MAX_N;
+  }();
+  return v;
+}
+
+// Matrices per wave for order n: the largest power of two P <= 64 that leaves
+// every lane at least one term (64 / P <= 2^(n-1)) and keeps the wave's
+// staged rows and column sums within 8 KiB of LDS.  The LDS bound was set by
+// a sweep of P at orders 4..14 (200,000 matrices each): more matrices per wave
+// mean fewer seeds per term but fewer resident waves, and 8 KiB picks the
+// fastest P, or one within 10% of it, at every point measured.
+// PERM_BATCH_PACK forces a value when it leaves every lane a term.
+int pack_for(int n, int C) {
+  const size_t per = sizeof(double) * (size_t)(n * n + n) * C;
+  auto ok = [&](int P, size_t budget) {
+    return P >= 1 && P <= 64 && (64 / P) <= (1 << (n - 1)) && (size_t)P * per <= budget;
+  };
+  if (const char *e = std::getenv("PERM_BATCH_PACK")) {
+    const int P = std::atoi(e);
+    if (P > 0 && (P & (P - 1)) == 0 && ok(P, 32768)) return P;
+  }
+  for (int P = 64; P >= 1; P >>= 1)
+    if (ok(P, 8192)) return P;
+  return 0;
+}
+
 BatchLaunch make_launch(const perm_batch_plan *p, const void *data, void *out) {
   BatchLaunch L;
   L.kind = p->kind;
@@ -129,9 +160,14 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
     d.first_slot = (uint32_t)slot;
     if (d.n > 0) {
       const int nbits = d.n - 1;
-      d.b = batch_block_log2(nbits);
-      const uint64_t nblocks = 1ull << (nbits - d.b);
-      d.nchunks = (uint32_t)((nblocks + 127) / 128);
+      if (d.n <= pack_max_n() && pack_for(d.n, kind == ENGINE_CPLX ? 2 : 1) > 0) {
+        d.b = 0;  // whole matrix in one wave's lane group: one slot
+        d.nchunks = 1;
+      } else {
+        d.b = batch_block_log2(nbits);
+        const uint64_t nblocks = 1ull << (nbits - d.b);
+        d.nchunks = (uint32_t)((nblocks + 127) / 128);
+      }
       slot += d.nchunks;
       by_n[d.n].push_back((uint32_t)i);
     }
@@ -154,10 +190,17 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
         item_chunk.push_back(c);
       }
     bk.item_end = (uint32_t)item_matrix.size();
-    const int bpc = std::max(1, batched_blocks_per_cu(kind, n));
-    const uint64_t waves_needed = bk.item_end - bk.item_begin;
-    const uint64_t groups = std::min<uint64_t>((uint64_t)cus * bpc, (waves_needed + 3) / 4);
-    bk.grid = (int)std::max<uint64_t>(1, groups);
+    const int pk = n <= pack_max_n() ? pack_for(n, kind == ENGINE_CPLX ? 2 : 1) : 0;
+    if (pk > 0) {
+      // one wave (workgroup) per `pk` matrices
+      bk.pack = pk;
+      bk.grid = (int)((bk.item_end - bk.item_begin + (uint32_t)pk - 1) / (uint32_t)pk);
+    } else {
+      const int bpc = std::max(1, batched_blocks_per_cu(kind, n));
+      const uint64_t waves_needed = bk.item_end - bk.item_begin;
+      const uint64_t groups = std::min<uint64_t>((uint64_t)cus * bpc, (waves_needed + 3) / 4);
+      bk.grid = (int)std::max<uint64_t>(1, groups);
+    }
     p->buckets.push_back(bk);
   }
   std::vector<double> ones(2 * BATCH_MAX_N);

@@ -89,6 +89,8 @@ struct BatchBucket {
   int n;
   uint32_t item_begin, item_end;
   int grid;
+  int pack = 0;  // > 0: small order, `pack` matrices per wave (batched_small.inc),
+                 // one item and one slot per matrix; 0: chunked per-order kernel
 };
 
 struct BatchLaunch {
@@ -182,6 +184,12 @@ hipError_t launch_combinatoric(int kind, int m, int n, perm_dtype dt, const void
 
 // Batched Glynn: the per-order persistent kernels and the per-matrix finish.
 hipError_t launch_batched(const BatchLaunch &L, hipStream_t s);
+// Orders up to BATCH_PACK_MAX_N can run several matrices per wave.
+#define BATCH_PACK_MAX_N 14
+hipError_t launch_batched_small_real(int n, const BatchBucket &bk, const BatchLaunch &L,
+                                     hipStream_t s);
+hipError_t launch_batched_small_cplx(int n, const BatchBucket &bk, const BatchLaunch &L,
+                                     hipStream_t s);
 int batched_blocks_per_cu(int kind, int n);  // resident 256-thread workgroups per CU
 
 // Writes the value 1 in the output type (the permanent of an empty matrix).
