@@ -14,7 +14,9 @@ Haar unitary, one graph launch) and the CPU oracle baseline.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -123,24 +125,33 @@ def suite(args):
         v = r.value()
         val = v[0] + v[1] if isinstance(v, tuple) else v
         rec = gold.get(name)
-        err = None
+        errs = {}
         if rec is not None:
             ref = rec["value"]
-            if isinstance(ref, str) and isinstance(val, float):
-                err = abs(val - int(ref)) / abs(int(ref)) if int(ref) else abs(val)
-            elif isinstance(ref, str):
-                err = 0 if int(ref) == val else abs(int(ref) - val)
-            elif "hi" in ref:
-                err = abs(val - (ref["hi"] + ref["lo"])) / abs(ref["hi"] + ref["lo"])
+            if isinstance(ref, str) and not isinstance(val, float):
+                errs["int_abs_diff"] = 0 if int(ref) == val else abs(int(ref) - val)
             else:
-                refc = complex(ref["re"]["hi"] + ref["re"]["lo"], ref["im"]["hi"] + ref["im"]["lo"])
-                err = abs(complex(val) - refc) / abs(refc)
+                if isinstance(ref, str):
+                    refv, pabs = int(ref), abs(int(ref))    # 0/1 input: per(|A|) = per(A)
+                elif "hi" in ref:
+                    refv, pabs = ref["hi"] + ref["lo"], rec["per_abs"]["hi"]
+                else:
+                    refv = complex(ref["re"]["hi"] + ref["re"]["lo"],
+                                   ref["im"]["hi"] + ref["im"]["lo"])
+                    pabs = rec["per_abs"]["hi"]
+                d = abs(complex(val) - complex(refv))
+                errs["rel_err_vs_oracle"] = d / abs(refv) if refv else d
+                errs["err_over_per_abs"] = d / pabs if pabs else d
+                # Sec. 4: digits lost = log10(relative error / machine epsilon), 0 if exact
+                errs["digits_lost"] = (max(0.0, math.log10(errs["rel_err_vs_oracle"] / 2.0 ** -52))
+                                       if d and refv else 0.0)
         km = float(np.median(kms))
+        digest = hashlib.sha256(np.ascontiguousarray(a.cpu().numpy()).tobytes()).hexdigest()[:16]
         print(json.dumps({"workload": name, "m": m, "n": n, "algorithm": algo,
                           "output": out or "default", "terms": terms, "reps": reps,
                           "kernel_ms": km, "wall_ms": float(np.median(walls)),
-                          "terms_per_s": terms / (km * 1e-3),
-                          "rel_err_vs_oracle" if not isinstance(err, int) else "int_abs_diff": err}),
+                          "terms_per_s": terms / (km * 1e-3), **errs,
+                          "input_sha256_16": digest}),
               flush=True)
     pg.profile_enable(False)
     batched(args)
