@@ -5,6 +5,7 @@ import pytest
 
 import oracle
 import workloads
+from tests.gpu_util import golden, ref_value
 
 pytestmark = pytest.mark.gpu
 U = 2.0 ** -53
@@ -147,7 +148,9 @@ def test_large_orders_use_many_chunks():
     import torch
 
     import paper_2510_03421_amd as pg
-    mats = [workloads.uniform(n, n, 900 + n) for n in (17, 20, 22, 24)]
+    # up to the batched limit n = 32; the last matrix is the 32 x 32 workload
+    mats = [workloads.uniform(n, n, 900 + n) for n in (17, 20, 22, 24, 28)]
+    mats.append(workloads.config_matrix("u32"))
     data, m, n, off, ld = pack(mats, np.float64)
     t = torch.from_numpy(data).cuda()
     plan = pg.BatchPlan(m, n, off, ld, t.dtype, out="dd")
@@ -157,6 +160,8 @@ def test_large_orders_use_many_chunks():
     for i, a in enumerate(mats):
         single = pg.glynn(torch.from_numpy(a).cuda(), out="dd").value()
         assert abs(got[i] - (single[0] + single[1])) <= 1e-12 * abs(single[0])
+    rec = golden()["u32"]
+    assert abs(got[-1] - ref_value(rec)) <= 1e-11 * abs(ref_value(rec))
     plan.close()
 
 
