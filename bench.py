@@ -170,16 +170,26 @@ def batched(args, count: int = 200_000, sample: int = 20_000, emit: bool = True)
     from paper_2510_03421_amd import _capi as C
     b = workloads.boson_batch(count, 4, 20, N=64, seed_u=6400, seed_idx=6401)
     data = torch.from_numpy(b.data).cuda()
-    plan = pg.BatchPlan(b.m, b.n, b.offset, b.ld, data.dtype, out="c128")
-    out = plan.new_output()
-    plan.run(data, out)          # capture
-    torch.cuda.synchronize()
     reps = max(1, min(args.steps, 10))
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        plan.run(data, out)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / reps
+
+    def time_plan(plan, out):
+        plan.run(data, out)      # capture (and, when autotuning, the timing of each packing)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.run(data, out)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    # matrices per wave of the small orders: the measured rule, and tuned on this batch
+    rule = pg.BatchPlan(b.m, b.n, b.offset, b.ld, data.dtype, out="c128")
+    out = rule.new_output()
+    t_rule = time_plan(rule, out)
+    rule_pack = {int(n): rule.packing(int(n)) for n in np.unique(b.n) if rule.packing(int(n))}
+    rule.close()
+    plan = pg.BatchPlan(b.m, b.n, b.offset, b.ld, data.dtype, out="c128", autotune=True)
+    t_batch = time_plan(plan, out)
+    tuned_pack = {int(n): plan.packing(int(n)) for n in np.unique(b.n) if plan.packing(int(n))}
     terms = float(np.sum(2.0 ** (b.n.astype(np.float64) - 1)))
     # per-matrix launches over a sample (same stream, same output type)
     single = torch.empty(2 * sample, dtype=torch.float64, device="cuda")
@@ -199,7 +209,8 @@ def batched(args, count: int = 200_000, sample: int = 20_000, emit: bool = True)
     maxdiff = float((vb - vs).abs().max())
     bound = float(torch.sqrt((out.view(-1, 2) ** 2).sum(1)).max())
     rec = {"workload": "batched_boson_200000_c128_n4..20", "count": count,
-           "terms": terms, "graph_ms": t_batch * 1e3,
+           "terms": terms, "graph_ms": t_batch * 1e3, "packing_autotuned": tuned_pack,
+           "graph_ms_rule_packing": t_rule * 1e3, "packing_rule": rule_pack,
            "perms_per_s": count / t_batch, "terms_per_s": terms / t_batch,
            "single_launch_perms_per_s": 1.0 / t_single, "single_launch_sample": sample,
            "speedup_vs_single_launches": t_single * count / t_batch,

@@ -108,6 +108,9 @@ typedef enum perm_algo {
                                return the exact value modulo 2^64 / 2^128 (for
                                Glynn: modulo 2^(128-(n-1)-v), v the power of two
                                in (n-m)!), sign-extended */
+#define PERM_BATCH_AUTOTUNE 0x4u /* perm_batch_plan_create: choose the matrices per
+                                    wave of every small order by timing on the
+                                    plan's first run (see perm_batch_plan_run) */
 
 /* Library version, PERM_VERSION. */
 int perm_version(void);
@@ -206,30 +209,49 @@ int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out
  * The Gray-code terms of each matrix are cut into chunks (work items); one
  * persistent kernel per matrix order serves all items of that order, every
  * item writes its own partial slot, and one finishing kernel adds each
- * matrix's slots in a fixed order -- results are bitwise reproducible. */
+ * matrix's slots in a fixed order -- results are bitwise reproducible for a
+ * given plan.  Orders n <= 14 run P matrices per wave instead (P a power of
+ * two, 64 / P lanes per matrix, the wave's rows staged in LDS): P follows a
+ * rule set by measurement (the largest P leaving every lane a term within
+ * 8 KiB of LDS), or, with PERM_BATCH_AUTOTUNE, the fastest P measured on the
+ * plan's own batch.  P changes how a matrix's terms are split over lanes, so
+ * results of plans with different P agree to rounding, not bitwise. */
 typedef struct perm_batch_plan perm_batch_plan;
 
 /* Build a plan (descriptors, work list, scratch) for a batch of shapes.
  * algo must be PERM_ALGO_GLYNN (PERM_E_UNSUPPORTED otherwise, and for integer
- * input/output or hM[b] > hN[b]); hN[b] > 32 gives PERM_E_TOO_LARGE.  The plan
- * is bound to the current device and owns its device memory.  Synchronous. */
+ * input/output or hM[b] > hN[b]); hN[b] > 32 gives PERM_E_TOO_LARGE.  flags:
+ * 0 or PERM_BATCH_AUTOTUNE (other bits PERM_E_INVALID).  The plan is bound to
+ * the current device and owns its device memory.  Synchronous. */
 int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
                            const int64_t *hOffset, const int64_t *hLd, perm_dtype dt,
                            perm_out ot, perm_algo algo, uint32_t flags, perm_batch_plan **plan);
 
 /* Run a plan on (dData, dOut), asynchronously on `stream`.  The first run for
- * a (dData, dOut) pair captures the launch sequence (counter reset, the
- * per-order kernels, the finishing kernel) into a hipGraph owned by the plan;
- * later runs with the same pointers replay it with one graph launch.  Runs of
- * one plan must not overlap (they share the plan's scratch). */
+ * a (dData, dOut) pair captures the launch sequence (the per-order kernels,
+ * the finishing kernel) into a hipGraph owned by the plan; later runs with the
+ * same pointers replay it with one graph launch.  Runs of one plan must not
+ * overlap (they share the plan's scratch).  With PERM_BATCH_AUTOTUNE the
+ * first run first times, for each small order, every admissible P (powers of
+ * two up to 64 that leave each lane a term and stage at most 32 KiB in LDS)
+ * on the plan's own stream after the work already queued on `stream`, three
+ * launches each, keeps the fastest and waits for the timings (this run is
+ * synchronous); the choice holds for the life of the plan. */
 int perm_batch_plan_run(perm_batch_plan *plan, const void *dData, void *dOut, void *stream);
+
+/* Matrices per wave the plan uses for order n: P >= 1 for a small order
+ * present in the batch, 0 for an order served by the chunked kernel or absent
+ * (and for n out of range).  After an autotuning plan's first run, the P it
+ * chose. */
+int perm_batch_plan_packing(const perm_batch_plan *plan, int n);
 
 /* Release the plan, its graph and its device memory (NULL is ignored).  The
  * caller must make sure no run of the plan is still executing. */
 int perm_batch_plan_destroy(perm_batch_plan *plan);
 
 /* One-shot convenience: create a plan, launch it without graph capture, wait
- * for the stream, destroy the plan. */
+ * for the stream, destroy the plan.  flags as for perm_batch_plan_create;
+ * PERM_BATCH_AUTOTUNE has no effect here (nothing is timed). */
 int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
                        const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
                        void *dOut, uint32_t flags, void *stream);

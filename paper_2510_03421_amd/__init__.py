@@ -185,7 +185,7 @@ class BatchPlan:
     (see perm_batch_plan_create).  ``run`` replays a captured hipGraph."""
 
     def __init__(self, m, n, offset, ld, dtype: torch.dtype, out: str | None = None,
-                 algo: str = "glynn", flags: int = 0):
+                 algo: str = "glynn", flags: int = 0, autotune: bool = False):
         import numpy as np
         self.m = np.ascontiguousarray(m, dtype=np.int32)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
@@ -197,8 +197,13 @@ class BatchPlan:
         self._h = ctypes.c_void_p()
         C.check(C.lib.perm_batch_plan_create(
             self.count, self.m.ctypes.data, self.n.ctypes.data, self.offset.ctypes.data,
-            self.ld.ctypes.data, self.dt, _OUT[self.kind], _ALGO_ID[algo], flags,
+            self.ld.ctypes.data, self.dt, _OUT[self.kind], _ALGO_ID[algo],
+            flags | (C.PERM_BATCH_AUTOTUNE if autotune else 0),
             ctypes.byref(self._h)), "perm_batch_plan_create")
+
+    def packing(self, n: int) -> int:
+        """Matrices per wave used for order n (0: chunked kernel or absent)."""
+        return int(C.lib.perm_batch_plan_packing(self._h, int(n)))
 
     def new_output(self, device="cuda") -> torch.Tensor:
         tdt, cnt = _OUTBUF[self.kind]

@@ -28,6 +28,7 @@ PERM_OUT_F64, PERM_OUT_C128, PERM_OUT_I64, PERM_OUT_I128, PERM_OUT_DD, PERM_OUT_
 PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN, PERM_ALGO_GLYNN_ESYM = 0, 1, 2, 3
 PERM_FLAG_WRAP = 0x1
 PERM_FLAG_PAD_ONES = 0x2
+PERM_BATCH_AUTOTUNE = 0x4
 
 _i32, _i64, _u32, _p, _d = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, \
     ctypes.c_double
@@ -54,6 +55,8 @@ lib.perm_batch_plan_create.restype = _i32
 lib.perm_batch_plan_run.argtypes = [_p, _p, _p, _p]
 lib.perm_batch_plan_run.restype = _i32
 lib.perm_batch_plan_destroy.argtypes = [_p]
+lib.perm_batch_plan_packing.argtypes = [_p, _i32]
+lib.perm_batch_plan_packing.restype = _i32
 lib.perm_batch_plan_destroy.restype = _i32
 lib.perm_glynn_batched.argtypes = [_i32, _p, _p, _p, _p, _i32, _p, _i32, _p, _u32, _p]
 lib.perm_glynn_batched.restype = _i32

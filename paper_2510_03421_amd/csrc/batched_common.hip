@@ -58,18 +58,19 @@ int batched_blocks_per_cu(int kind, int n) {
   return n <= 20 ? batched_occ_real_a(n) : batched_occ_real_b(n);
 }
 
+hipError_t launch_batched_bucket(const BatchLaunch &L, int i, hipStream_t s) {
+  const BatchBucket &bk = L.buckets[i];
+  if (bk.pack > 0)
+    return L.kind == ENGINE_CPLX ? launch_batched_small_cplx(bk.n, bk, L, s)
+                                 : launch_batched_small_real(bk.n, bk, L, s);
+  if (L.kind == ENGINE_CPLX)
+    return bk.n <= 20 ? batched_launch_cplx_a(bk.n, bk, L, s) : batched_launch_cplx_b(bk.n, bk, L, s);
+  return bk.n <= 20 ? batched_launch_real_a(bk.n, bk, L, s) : batched_launch_real_b(bk.n, bk, L, s);
+}
+
 hipError_t launch_batched(const BatchLaunch &L, hipStream_t s) {
   hipError_t e = hipSuccess;
-  for (int i = 0; i < L.nbuckets && e == hipSuccess; ++i) {
-    const BatchBucket &bk = L.buckets[i];
-    if (bk.pack > 0)
-      e = L.kind == ENGINE_CPLX ? launch_batched_small_cplx(bk.n, bk, L, s)
-                                : launch_batched_small_real(bk.n, bk, L, s);
-    else if (L.kind == ENGINE_CPLX)
-      e = bk.n <= 20 ? batched_launch_cplx_a(bk.n, bk, L, s) : batched_launch_cplx_b(bk.n, bk, L, s);
-    else
-      e = bk.n <= 20 ? batched_launch_real_a(bk.n, bk, L, s) : batched_launch_real_b(bk.n, bk, L, s);
-  }
+  for (int i = 0; i < L.nbuckets && e == hipSuccess; ++i) e = launch_batched_bucket(L, i, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batched_finish_kernel, dim3((L.count + 255) / 256), dim3(256), 0, s, L.kind,
                      L.mats, L.count, L.slots, L.ot, L.out);

@@ -28,6 +28,10 @@ struct perm_batch_plan {
   hipGraphExec_t exec = nullptr;
   const void *g_data = nullptr;
   void *g_out = nullptr;
+  // PERM_BATCH_AUTOTUNE: the matrices per wave of the small orders are timed
+  // on the first run
+  bool autotune = false;
+  bool tuned = false;
 };
 
 namespace {
@@ -75,17 +79,21 @@ int pack_max_n() {
 // mean fewer seeds per term but fewer resident waves, and 8 KiB picks the
 // fastest P, or one within 10% of it, at every point measured.
 // PERM_BATCH_PACK forces a value when it leaves every lane a term.
-int pack_for(int n, int C) {
+constexpr size_t kPackLdsMax = 32768;  // the largest staging measured (and tuned over)
+
+bool pack_admissible(int n, int C, int P, size_t budget) {
   const size_t per = sizeof(double) * (size_t)(n * n + n) * C;
-  auto ok = [&](int P, size_t budget) {
-    return P >= 1 && P <= 64 && (64 / P) <= (1 << (n - 1)) && (size_t)P * per <= budget;
-  };
+  return P >= 1 && P <= 64 && (P & (P - 1)) == 0 && (64 / P) <= (1 << (n - 1)) &&
+         (size_t)P * per <= budget;
+}
+
+int pack_for(int n, int C) {
   if (const char *e = std::getenv("PERM_BATCH_PACK")) {
     const int P = std::atoi(e);
-    if (P > 0 && (P & (P - 1)) == 0 && ok(P, 32768)) return P;
+    if (pack_admissible(n, C, P, kPackLdsMax)) return P;
   }
   for (int P = 64; P >= 1; P >>= 1)
-    if (ok(P, 8192)) return P;
+    if (pack_admissible(n, C, P, 8192)) return P;
   return 0;
 }
 
@@ -106,6 +114,54 @@ BatchLaunch make_launch(const perm_batch_plan *p, const void *data, void *out) {
   return L;
 }
 
+// Times every admissible P of each small order on the caller's data (three
+// launches of that order's kernel alone, the first not counted) and keeps the
+// fastest.  The launches run on the plan's stream after the work queued on
+// `s`; the slots they write are written again by the run that follows.
+int autotune_packing(perm_batch_plan *p, const void *dData, void *dOut, hipStream_t s) {
+  hipEvent_t ready = nullptr, e0 = nullptr, e1 = nullptr;
+  int rc = PERM_OK;
+  if (hipEventCreate(&ready) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    rc = PERM_E_HIP;
+  hipStream_t cs = p->capture_stream;
+  if (!rc && (hipEventRecord(ready, s) != hipSuccess || hipStreamWaitEvent(cs, ready, 0) != hipSuccess))
+    rc = PERM_E_HIP;
+  const int C = p->kind == ENGINE_CPLX ? 2 : 1;
+  BatchLaunch L = make_launch(p, dData, dOut);
+  for (size_t i = 0; i < p->buckets.size() && !rc; ++i) {
+    BatchBucket &bk = p->buckets[i];
+    if (bk.pack <= 0) continue;
+    const uint32_t items = bk.item_end - bk.item_begin;
+    int best = bk.pack;
+    float best_ms = 0.0f;
+    for (int P = 1; P <= 64 && !rc; P <<= 1) {
+      if (!pack_admissible(bk.n, C, P, kPackLdsMax)) continue;
+      bk.pack = P;
+      bk.grid = (int)((items + (uint32_t)P - 1) / (uint32_t)P);
+      for (int r = 0; r < 3 && !rc; ++r) {
+        float ms = 0.0f;
+        if (hipEventRecord(e0, cs) != hipSuccess || launch_batched_bucket(L, (int)i, cs) != hipSuccess ||
+            hipEventRecord(e1, cs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = PERM_E_HIP;
+          break;
+        }
+        if (r > 0 && (best_ms == 0.0f || ms < best_ms)) {
+          best_ms = ms;
+          best = P;
+        }
+      }
+    }
+    bk.pack = best;
+    bk.grid = (int)((items + (uint32_t)best - 1) / (uint32_t)best);
+  }
+  if (ready) (void)hipEventDestroy(ready);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return rc;
+}
+
 template <class T>
 int upload(T **dst, const std::vector<T> &src) {
   const size_t bytes = sizeof(T) * std::max<size_t>(1, src.size());
@@ -123,9 +179,9 @@ extern "C" {
 int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
                            const int64_t *hOffset, const int64_t *hLd, perm_dtype dt,
                            perm_out ot, perm_algo algo, uint32_t flags, perm_batch_plan **plan) {
-  (void)flags;
   if (!plan) return PERM_E_INVALID;
   *plan = nullptr;
+  if (flags & ~PERM_BATCH_AUTOTUNE) return PERM_E_INVALID;
   if (count < 0 || (count > 0 && (!hM || !hN || !hOffset || !hLd))) return PERM_E_INVALID;
   int kind = 0;
   int rc = engine_kind_for(dt, ot, kind);
@@ -146,6 +202,7 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
   p->count = count;
   p->kind = kind;
   p->ot = ot;
+  p->autotune = (flags & PERM_BATCH_AUTOTUNE) != 0;
   // descriptors and slots
   std::vector<BatchMatrix> mats(count);
   uint64_t slot = 0;
@@ -231,6 +288,11 @@ int perm_batch_plan_run(perm_batch_plan *p, const void *dData, void *dOut, void 
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != p->dev) return PERM_E_INVALID;
+  if (p->autotune && !p->tuned) {
+    const int rc = autotune_packing(p, dData, dOut, s);
+    if (rc) return rc;
+    p->tuned = true;
+  }
   if (!p->exec || p->g_data != dData || p->g_out != dOut) {
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
@@ -257,6 +319,13 @@ int perm_batch_plan_run(perm_batch_plan *p, const void *dData, void *dOut, void 
     p->g_out = dOut;
   }
   return hipGraphLaunch(p->exec, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
+}
+
+int perm_batch_plan_packing(const perm_batch_plan *p, int n) {
+  if (!p || n < 1 || n > BATCH_MAX_N) return 0;
+  for (const BatchBucket &bk : p->buckets)
+    if (bk.n == n) return bk.pack;
+  return 0;
 }
 
 int perm_batch_plan_destroy(perm_batch_plan *p) {

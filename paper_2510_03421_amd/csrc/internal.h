@@ -184,6 +184,8 @@ hipError_t launch_combinatoric(int kind, int m, int n, perm_dtype dt, const void
 
 // Batched Glynn: the per-order persistent kernels and the per-matrix finish.
 hipError_t launch_batched(const BatchLaunch &L, hipStream_t s);
+// the kernel of bucket i alone (no finishing kernel)
+hipError_t launch_batched_bucket(const BatchLaunch &L, int i, hipStream_t s);
 // Orders up to BATCH_PACK_MAX_N can run several matrices per wave.
 #define BATCH_PACK_MAX_N 14
 hipError_t launch_batched_small_real(int n, const BatchBucket &bk, const BatchLaunch &L,

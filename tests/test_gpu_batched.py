@@ -144,6 +144,49 @@ def test_packed_orders_strided_rectangular_and_partial_waves(cplx):
     plan.close()
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_autotuned_packing(cplx):
+    """PERM_BATCH_AUTOTUNE: every small order gets an admissible matrices-per-
+    wave count, the values agree with the oracle and with the rule-packed plan,
+    and later runs replay the tuned graph bitwise."""
+    import torch
+
+    import paper_2510_03421_amd as pg
+    C = 2 if cplx else 1
+    mats = []
+    for n in list(range(2, 15)) + [16, 18]:
+        for k in range(9):
+            mats.append(workloads.complex_gauss(n, n, 7000 + 20 * n + k) if cplx else
+                        workloads.uniform(n, n, 7000 + 20 * n + k))
+    data, m, n, off, ld = pack(mats, np.complex128 if cplx else np.float64)
+    t = torch.from_numpy(data).cuda()
+    kind = "cdd" if cplx else "dd"
+    tuned = pg.BatchPlan(m, n, off, ld, t.dtype, out=kind, autotune=True)
+    rule = pg.BatchPlan(m, n, off, ld, t.dtype, out=kind)
+    out_t, out_r = tuned.new_output(), rule.new_output()
+    tuned.run(t, out_t)
+    rule.run(t, out_r)
+    got_t = to_values(out_t, kind, len(mats))
+    got_r = to_values(out_r, kind, len(mats))
+    for order in range(2, 15):
+        P = tuned.packing(order)
+        assert P >= 1 and P & (P - 1) == 0 and 64 // P <= 2 ** (order - 1), (order, P)
+        assert P * (order * order + order) * C * 8 <= 32768, (order, P)
+        assert rule.packing(order) >= 1
+    assert tuned.packing(16) == 0 and tuned.packing(18) == 0 and tuned.packing(15) == 0
+    for i, a in enumerate(mats):
+        ref = complex(oracle.per_laplace(a))
+        scale = float(oracle.per_laplace(np.abs(a)))
+        assert abs(got_t[i] - ref) <= 1e-11 * scale, (i, a.shape, got_t[i], ref)
+        assert abs(got_t[i] - got_r[i]) <= 1e-12 * scale, (i, a.shape)
+    first = out_t.clone()
+    tuned.run(t, out_t)
+    torch.cuda.synchronize()
+    assert torch.equal(first, out_t)
+    tuned.close()
+    rule.close()
+
+
 def test_large_orders_use_many_chunks():
     import torch
 
@@ -186,3 +229,6 @@ def test_empty_batch_and_errors():
     with pytest.raises(pg.PermError) as ex:        # integer batches are not served
         pg.BatchPlan(one, one, np.zeros(1, np.int64), np.array([3]), torch.int64)
     assert ex.value.status == -5
+    with pytest.raises(pg.PermError) as ex:        # a flag batches do not take
+        pg.BatchPlan(one, one, np.zeros(1, np.int64), np.array([3]), torch.float64, flags=0x1)
+    assert ex.value.status == -1
