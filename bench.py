@@ -10,6 +10,8 @@ Haar unitary, one graph launch) and the CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched]
     python bench.py --suite      (every workload configuration, one line each)
+    python bench.py --selector-stream   (single permanents of mixed shapes under
+                                          the selector and fixed-algorithm policies)
 """
 from __future__ import annotations
 
@@ -155,6 +157,7 @@ def suite(args):
               flush=True)
     pg.profile_enable(False)
     batched(args)
+    selector_stream(args)
 
 
 def batched(args, count: int = 200_000, sample: int = 20_000, emit: bool = True):
@@ -222,6 +225,91 @@ def batched(args, count: int = 200_000, sample: int = 20_000, emit: bool = True)
     return rec
 
 
+def selector_stream(args, cap_ms: float = 100.0, emit: bool = True):
+    """A stream of single permanents of mixed shapes and dtypes: the held-out
+    selector cases on which every algorithm finishes within `cap_ms` by the
+    stored MI355X timings, each computed by one call under four policies --
+    perm_auto with the shipped network, perm_auto with the threshold table
+    (both may run the e_m form for m < n), the first choice among the three
+    algorithms of the network and of the table alone, always Glynn (Ryser
+    where Glynn's limits refuse), always Ryser (Glynn where Ryser's refuse).  Permanents per second over the stream, one warm pass per
+    policy first.  Also the totals the stored timings give over all held-out
+    cases (where a wrong choice can cost minutes)."""
+    import numpy as np
+    import torch
+
+    import paper_2510_03421_amd as pg
+    import workloads
+    from paper_2510_03421_amd import _capi as C
+    from paper_2510_03421_amd import train_selector as T
+    d = T.load_timings(os.path.join(ROOT, "paper_2510_03421_amd", "data",
+                                    "selector_timings_mi355x.csv"))
+    _, te = T.split(len(d["m"]))
+    keep = [int(i) for i in te if np.nanmax(d["ms"][i]) <= cap_ms]
+    cases = workloads.selector_cases(5000, seed=5000)
+    stream = []
+    for i in keep:
+        a = workloads.case_matrix(cases[int(d["i"][i])])
+        flags = C.PERM_FLAG_WRAP if a.dtype == np.uint8 else 0   # as the timings were taken
+        stream.append((torch.from_numpy(np.ascontiguousarray(a)).cuda(), flags,
+                       float(np.count_nonzero(a)) / a.size))
+
+    def first_accepting(fns):
+        def run(a, flags, density):
+            for k, fn in enumerate(fns):
+                try:
+                    return fn(a, flags=flags)
+                except pg.PermError as e:
+                    if e.status != C.PERM_E_TOO_LARGE or k + 1 == len(fns):
+                        raise
+        return run
+
+    auto = lambda a, flags, density: pg.auto(a, flags=flags, density=density)
+    fns = {"combinatoric": pg.combinatoric, "ryser": pg.ryser, "glynn": pg.glynn}
+
+    def first_choice(weights):
+        # the selector's first choice among the three algorithms (no e_m form),
+        # decided before the stream runs
+        pg.selector_load(weights)
+        picks = [fns[pg.select(*sorted(a.shape), a.dtype, density)[0]] for a, _, density in stream]
+        it = iter(picks * 2)
+        return lambda a, flags, density: next(it)(a, flags=flags)
+
+    policies = {"auto_network": (pg.SELECTOR_WEIGHTS, auto), "auto_table": (None, auto),
+                "network_first_choice": (None, first_choice(pg.SELECTOR_WEIGHTS)),
+                "table_first_choice": (None, first_choice(None)),
+                "always_glynn": (None, first_accepting([pg.glynn, pg.ryser])),
+                "always_ryser": (None, first_accepting([pg.ryser, pg.glynn]))}
+    rate, wall = {}, {}
+    for name, (weights, fn) in policies.items():
+        pg.selector_load(weights)
+        for timed in (False, True):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for a, flags, density in stream:
+                fn(a, flags, density)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        wall[name], rate[name] = dt, len(stream) / dt
+    pg.selector_load(pg.SELECTOR_WEIGHTS)
+    # the whole held-out set, from the stored timings
+    ms = d["ms"][te]
+    avail = ~np.isnan(ms)
+    rows = np.arange(len(te))
+    est = {"best_per_case": float(np.nanmin(ms, axis=1).sum() / 1e3)}
+    for name, w in (("auto_network", pg.SELECTOR_WEIGHTS), ("auto_table", None)):
+        est[name] = float(ms[rows, T.library_choices(d, te, w)].sum() / 1e3)
+    pg.selector_load(pg.SELECTOR_WEIGHTS)
+    est["always_glynn"] = float(np.where(avail[:, 2], ms[:, 2], ms[:, 1]).sum() / 1e3)
+    est["always_ryser"] = float(np.where(avail[:, 1], ms[:, 1], ms[:, 2]).sum() / 1e3)
+    rec = {"workload": f"selector_stream_heldout_{len(stream)}_cases_all_algorithms_le_{cap_ms:g}ms",
+           "cases": len(stream), "perms_per_s": rate, "wall_s": wall,
+           "heldout_all_1000_estimated_s": est}
+    if emit:
+        print(json.dumps(rec), flush=True)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,7 +324,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="instead of the benchmark, copy a 1 GiB device buffer --steps "
                          "times (a kernel of known HBM traffic for counter scaling)")
+    ap.add_argument("--selector-stream", action="store_true",
+                    help="instead of the benchmark, only the selector stream record "
+                         "(also part of --suite)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this library computes one permanent per GPU call and is "
+              "measured on a single GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    if args.selector_stream:
+        selector_stream(args)
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -250,10 +348,6 @@ def main():
     if args.suite:
         suite(args)
         return
-    if args.gpus != 1:
-        print("bench.py: this library computes one permanent per GPU call and is "
-              "measured on a single GPU; --gpus must be 1", file=sys.stderr)
-        sys.exit(2)
 
     import numpy as np
     import torch
