@@ -6,9 +6,11 @@ update table, 2^31 Gray-code terms (closed-form re-seed per lane block, one
 row update and one 32-factor product per term, compensated accumulation),
 the deterministic reduction and the final scaling.  Prints one JSON line,
 which also carries the batched record (200,000 complex submatrices of a
-Haar unitary, one graph launch) and the CPU oracle baseline.
+Haar unitary, one graph launch), the selector stream record (single
+permanents of mixed shapes under perm_auto and fixed algorithms) and the CPU
+oracle baseline.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-selector]
     python bench.py --suite      (every workload configuration, one line each)
     python bench.py --selector-stream   (single permanents of mixed shapes under
                                           the selector and fixed-algorithm policies)
@@ -324,6 +326,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="instead of the benchmark, copy a 1 GiB device buffer --steps "
                          "times (a kernel of known HBM traffic for counter scaling)")
+    ap.add_argument("--no-selector", action="store_true",
+                    help="skip the selector stream record")
     ap.add_argument("--selector-stream", action="store_true",
                     help="instead of the benchmark, only the selector stream record "
                          "(also part of --suite)")
@@ -431,6 +435,9 @@ def main():
         # the metric's second part: batched permanents per second (one graph
         # launch) against one perm_glynn call per matrix on a sample
         line["batched"] = batched(args, sample=2_000, emit=False)
+    if not args.no_selector:
+        # single permanents of mixed shapes: perm_auto against fixed algorithms
+        line["selector"] = selector_stream(args, emit=False)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(a_host)
     print(json.dumps(line), flush=True)
