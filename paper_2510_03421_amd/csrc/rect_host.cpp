@@ -88,8 +88,10 @@ int device_tables(int l, DevTables &out) {
     if (hipMalloc((void **)&d, bytes) != hipSuccess) return PERM_E_HIP;
     if (!t.trans.empty() &&
         hipMemcpy(d, t.trans.data(), sizeof(uint32_t) * t.trans.size(), hipMemcpyHostToDevice) !=
-            hipSuccess)
+            hipSuccess) {
+      (void)hipFree(d);
       return PERM_E_HIP;
+    }
     trans_cache[key] = d;
   }
   if (!binom_cache.count(dev)) {
@@ -98,8 +100,10 @@ int device_tables(int l, DevTables &out) {
       for (int k = 0; k <= 64; ++k) b[x * 65 + k] = binom_u64(x, k);
     uint64_t *d = nullptr;
     if (hipMalloc((void **)&d, sizeof(uint64_t) * b.size()) != hipSuccess) return PERM_E_HIP;
-    if (hipMemcpy(d, b.data(), sizeof(uint64_t) * b.size(), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(d, b.data(), sizeof(uint64_t) * b.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d);
       return PERM_E_HIP;
+    }
     binom_cache[dev] = d;
   }
   out.trans = trans_cache[key];
