@@ -228,3 +228,39 @@ def test_training_on_stored_timings_beats_the_table():
     finally:
         pg.selector_load(pg.SELECTOR_WEIGHTS)
     assert np.mean(mlp) < np.mean(table), (np.mean(mlp), np.mean(table))
+
+
+def test_host_choice_matches_the_gpu_forward_on_the_shipped_network():
+    """perm_auto evaluates the shipped network on the host; on every stored
+    selector case its choice equals the argmin, over the algorithms the case
+    admits, of the GPU forward kernel's predictions (up to FP32 near-ties)."""
+    import torch
+
+    import paper_2510_03421_amd as pg
+    from paper_2510_03421_amd import selector as S
+    from paper_2510_03421_amd import train_selector as TS
+    toks = open(pg.SELECTOR_WEIGHTS).read().split()
+    norm = np.array(toks[toks.index("norm") + 1:toks.index("norm") + 9], dtype=np.float32)
+    params = np.array(toks[toks.index("mlp") + 1:], dtype=np.float32)
+    assert params.size == 4675
+    d = TS.load_timings(os.path.join(os.path.dirname(pg.__file__), "data",
+                                     "selector_timings_mi355x.csv"))
+    tdt = {"f64": torch.float64, "c128": torch.complex128, "b8": torch.uint8}
+    x = np.stack([S.features(int(m), int(n), tdt[dt], float(de))
+                  for m, n, dt, de in zip(d["m"], d["n"], d["dtype"], d["density"])])
+    y = S.mlp_forward(cu(params), cu(norm), cu(x.astype(np.float32))).cpu().numpy()
+    y = y.astype(np.float64)
+    avail = ~np.isnan(d["ms"])
+    best = np.argmin(np.where(avail, y, np.inf), axis=1)
+    pg.selector_load(pg.SELECTOR_WEIGHTS)
+    order = list(S.ALGO_ORDER)
+    near_ties = 0
+    for i in range(len(best)):
+        name, from_net = pg.select(int(d["m"][i]), int(d["n"][i]), tdt[d["dtype"][i]],
+                                   float(d["density"][i]))
+        assert from_net
+        ch = order.index(name)
+        if ch != best[i]:
+            near_ties += 1
+            assert abs(y[i, ch] - y[i, best[i]]) <= 1e-4 * (1.0 + abs(y[i, ch])), (i, y[i])
+    assert near_ties <= 5
