@@ -106,6 +106,9 @@ def suite(args):
             ("u20x40", "ryser", None), ("u20x40", "glynn", None), ("u20x40", "glynn_esym", None),
             ("b16x48", "ryser", "i128"), ("b16x48", "glynn_esym", "i128"),
             ("b16x48", "glynn_esym", "f64"), ("u36", "glynn", "dd")]
+    if args.only:
+        keep = [tuple(x.split(":")) for x in args.only.split(",")]
+        runs = [r for r in runs if (r[0], r[1]) in keep or (r[0], r[1], r[2] or "default") in keep]
     fn = {"glynn": pg.glynn, "ryser": pg.ryser, "combinatoric": pg.combinatoric,
           "glynn_esym": pg.glynn_esym}
     pg.profile_enable(True)
@@ -158,8 +161,10 @@ def suite(args):
                           "input_sha256_16": digest}),
               flush=True)
     pg.profile_enable(False)
-    batched(args)
-    selector_stream(args)
+    if not args.no_batched:
+        batched(args)
+    if not args.no_selector:
+        selector_stream(args)
 
 
 def batched(args, count: int = 200_000, sample: int = 20_000, emit: bool = True):
@@ -323,6 +328,9 @@ def main():
     ap.add_argument("--suite", action="store_true",
                     help="instead of the one contract line, time every workload "
                          "configuration (one JSON line each)")
+    ap.add_argument("--only", default="",
+                    help="with --suite: comma-separated workload:algorithm[:output] "
+                         "filters, e.g. u32:ryser,b16x48:glynn_esym:i128")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="instead of the benchmark, copy a 1 GiB device buffer --steps "
                          "times (a kernel of known HBM traffic for counter scaling)")

@@ -29,25 +29,47 @@ int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, i
     if (rc) return rc;
   }
   const int cus = device_cus();
-  if (cus <= 0) return PERM_E_HIP;
-  const uint64_t threads = (uint64_t)total;
-  int grid = (int)std::min<uint64_t>((uint64_t)cus * 8, (threads + 255) / 256);
-  grid = std::max(grid, 1);
-  uint64_t run = (uint64_t)total;
+  const int bpc = combinatoric_blocks_per_cu(kind, M, N);
+  if (cus <= 0 || bpc <= 0) return PERM_E_HIP;
+  // prefix length q: the shortest whose prefix count gives every resident lane
+  // at least four prefixes (all rows when the maps fit the lanes); rounds of
+  // T lanes, T the smallest multiple of 256 covering the prefixes in that
+  // many rounds
+  const uint64_t lanes_max = (uint64_t)cus * (uint64_t)bpc * 256u;
+  CombPlan c;
+  c.q = M;
+  if ((uint64_t)total > lanes_max) {
+    u128_host p = 1;
+    for (int q = 0; q <= M; ++q) {
+      if (q > 0) p *= (u128_host)(N - q + 1);
+      if (p >= (u128_host)4 * lanes_max) {
+        c.q = q;
+        break;
+      }
+    }
+  }
+  u128_host prefixes = 1;
+  for (int i = 0; i < c.q; ++i) prefixes *= (u128_host)(N - i);
+  c.prefixes = (uint64_t)prefixes;
+  c.suffixes = (uint64_t)(total / prefixes);
+  const uint64_t rounds = (c.prefixes + lanes_max - 1) / lanes_max;
+  const uint64_t T = ((c.prefixes + rounds - 1) / rounds + 255) / 256 * 256;
+  c.grid = (int)(T / 256);
+  c.rounds = (uint32_t)rounds;
   const double f = tune_fraction();
   if (f < 1.0) {
-    // a prefix of the maps, still spread over every thread
-    const uint64_t floor_run = std::min<uint64_t>(run, (uint64_t)grid * 256);
-    run = std::max<uint64_t>(floor_run, (uint64_t)std::llround((double)run * f));
-    run = std::min<uint64_t>(run, (uint64_t)total);
+    // whole rounds of prefixes, at least one
+    c.rounds = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(rounds, (uint64_t)std::llround((double)rounds * f)));
   }
-  tune_record((double)run / (double)(uint64_t)total);
+  const uint64_t ran = std::min<uint64_t>(c.prefixes, (uint64_t)c.rounds * T) * c.suffixes;
+  tune_record((double)ran / (double)(uint64_t)total);
+  const int grid = c.grid;
   const int C = kind == ENGINE_CPLX ? 2 : 1;
   double *part = nullptr;
   if (hipMallocAsync((void **)&part, sizeof(double) * 2 * C * (size_t)grid, s) != hipSuccess)
     return PERM_E_HIP;
   profile_begin(s);
-  hipError_t e = launch_combinatoric(kind, M, N, dt, dA, lda, tr, run, grid, part, s);
+  hipError_t e = launch_combinatoric(kind, M, N, dt, dA, lda, tr, c, part, s);
   profile_end(s);
   if (e == hipSuccess) {
     Finish f;

@@ -177,10 +177,19 @@ hipError_t launch_ryser_rect_real(const RectWalk &w, int grid, void *partials, h
 hipError_t launch_ryser_rect_cplx(const RectWalk &w, int grid, void *partials, hipStream_t s);
 hipError_t launch_ryser_rect_int(const RectWalk &w, int grid, void *partials, hipStream_t s);
 
-// The definition: `total` = n!/(n-m)! maps split over grid x 256 threads, one
-// partial per workgroup.
+// The definition: the n!/(n-m)! maps are `prefixes` prefixes (rows 0..q-1)
+// times `suffixes` suffixes; T = grid x 256 lanes take the prefixes t, t + T,
+// ... for `rounds` rounds (prefixes <= rounds T) and walk all suffixes of
+// each.  One partial per workgroup.
+struct CombPlan {
+  int q = 0;
+  uint64_t prefixes = 1, suffixes = 1;
+  uint32_t rounds = 1;
+  int grid = 1;
+};
 hipError_t launch_combinatoric(int kind, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
-                               int tr, uint64_t total, int grid, void *partials, hipStream_t s);
+                               int tr, const CombPlan &c, void *partials, hipStream_t s);
+int combinatoric_blocks_per_cu(int kind, int m, int n);  // resident 256-thread workgroups per CU
 
 // Batched Glynn: the per-order persistent kernels and the per-matrix finish.
 hipError_t launch_batched(const BatchLaunch &L, hipStream_t s);
