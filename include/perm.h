@@ -298,7 +298,8 @@ int perm_selector_features(int m, int n, perm_dtype dt, double density, float *x
  * run): Glynn and square Ryser run fewer Gray-code blocks per lane (never
  * fewer than two), in rectangular Ryser every wave stops after that fraction
  * of its share of the work (its last item's walks cut short), the
- * combinatoric sum runs a prefix of the maps.  *fraction_run (may be NULL)
+ * combinatoric sum runs whole rounds of its map prefixes (at least one), so
+ * its x can differ from `fraction` by a round.  *fraction_run (may be NULL)
  * receives the fraction x actually run.  The value computed
  * is discarded.  Errors: those of the algorithm's entry point, and
  * PERM_E_INVALID for fraction outside (0, 1], reps < 1 or ms NULL.
