@@ -140,8 +140,9 @@ int perm_profile_last(double *ms);
  * summed in reflected Gray-code order; for m < n the matrix is padded with
  * n - m rows of ones and the sum divided by (n-m)! (Eq. glynn_filled_matrix,
  * Eq. glynn_rectangle).  With floating-point outputs the padding rows hold
- * c = 2^e instead, e = round(log2(rms(A) sqrt(m) / (n-m))) computed on the
- * device, and the sum is divided by (n-m)! c^(n-m) (exact rescaling:
+ * c = 2^e instead, e = round(log2(rms(A) sqrt(m) / (n-m))) (sqrt(2m) in place
+ * of sqrt(m) for complex input) computed on the device, and the sum is
+ * divided by (n-m)! c^(n-m) (exact rescaling:
  * per([A; cJ]) = c^(n-m) per([A; J])); with rows of ones the padding
  * dominates the column sums and the sum loses most of its digits.
  * PERM_FLAG_PAD_ONES keeps the value 1.  Integer outputs always pad with
@@ -203,8 +204,11 @@ int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out
  * hLd[b] >= hN[b] (elements), starting at element offset hOffset[b].  The
  * shape arrays are HOST pointers, read during the call only.  dOut receives
  * `count` values of the output type, contiguous.  Supported: Glynn's formula
- * (square, and rectangular by padding with rows of ones) for PERM_F64 and
- * PERM_C128 input.  A matrix with hM[b] = 0 has permanent 1.
+ * (square, and rectangular by padding) for PERM_F64 and PERM_C128 input.  The
+ * padding rows of a rectangular matrix hold 2^e with e chosen on the device
+ * from that matrix's data as for perm_glynn, and the result is rescaled
+ * exactly; PERM_FLAG_PAD_ONES pads with rows of ones as Eq.
+ * glynn_filled_matrix prints it.  A matrix with hM[b] = 0 has permanent 1.
  *
  * The Gray-code terms of each matrix are cut into chunks (work items); one
  * persistent kernel per matrix order serves all items of that order, every
@@ -221,15 +225,17 @@ typedef struct perm_batch_plan perm_batch_plan;
 /* Build a plan (descriptors, work list, scratch) for a batch of shapes.
  * algo must be PERM_ALGO_GLYNN (PERM_E_UNSUPPORTED otherwise, and for integer
  * input/output or hM[b] > hN[b]); hN[b] > 32 gives PERM_E_TOO_LARGE.  flags:
- * 0 or PERM_BATCH_AUTOTUNE (other bits PERM_E_INVALID).  The plan is bound to
+ * PERM_BATCH_AUTOTUNE and/or PERM_FLAG_PAD_ONES (other bits PERM_E_INVALID).
+ * The plan is bound to
  * the current device and owns its device memory.  Synchronous. */
 int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
                            const int64_t *hOffset, const int64_t *hLd, perm_dtype dt,
                            perm_out ot, perm_algo algo, uint32_t flags, perm_batch_plan **plan);
 
 /* Run a plan on (dData, dOut), asynchronously on `stream`.  The first run for
- * a (dData, dOut) pair captures the launch sequence (the per-order kernels,
- * the finishing kernel) into a hipGraph owned by the plan; later runs with the
+ * a (dData, dOut) pair captures the launch sequence (the padding exponents of
+ * rectangular matrices, the per-order kernels, the finishing kernel) into a
+ * hipGraph owned by the plan; later runs with the
  * same pointers replay it with one graph launch.  Runs of one plan must not
  * overlap (they share the plan's scratch).  With PERM_BATCH_AUTOTUNE the
  * first run first times, for each small order, every admissible P (powers of

@@ -109,7 +109,8 @@ def _run(fn, a, out, flags):
 
 
 def glynn(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:
-    """Glynn's formula (square; rectangular via padding with rows of ones)."""
+    """Glynn's formula (square; rectangular via padding rows of 2^e scaled to
+    the data, or of ones with flags=PERM_FLAG_PAD_ONES)."""
     return _run(C.lib.perm_glynn, a, out, flags)
 
 

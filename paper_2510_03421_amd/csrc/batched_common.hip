@@ -1,11 +1,35 @@
-// Batched Glynn: per-matrix finishing kernel and the launch sequence (one
-// kernel per matrix order -- packed small orders or chunked persistent ones --
-// then the finish).
+// Batched Glynn: the padding exponents of rectangular matrices, the launch
+// sequence (one kernel per matrix order -- packed small orders or chunked
+// persistent ones -- then the finish) and the per-matrix finishing kernel.
 #include "device_common.h"
 #include "internal.h"
+#include "pad_model.h"
 
 namespace permgpu {
 namespace {
+
+// per rectangular matrix (one wave each): the padding exponent, chosen by
+// pad_exponent from the matrix's mean square as for single matrices
+__global__ __launch_bounds__(64) void batched_pad_kernel(int kind, BatchMatrix *__restrict__ mats,
+                                                         int count, const void *data) {
+  __shared__ float f[kPadCandidates];
+  const int i = blockIdx.x;
+  if (i >= count) return;
+  const BatchMatrix d = mats[i];
+  if (d.m <= 0 || d.m >= d.n) return;
+  const int C = kind == ENGINE_CPLX ? 2 : 1;
+  const double *A = (const double *)data + (size_t)d.offset * C;
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < d.m * d.n * C; e += 64) {
+    const int r = e / (d.n * C), k = e % (d.n * C);
+    const double x = A[(size_t)r * d.ld * C + k];
+    acc += x * x;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  acc = __shfl(acc, 0, 64);  // one value in every lane (the butterfly's order differs by lane)
+  const int x = pad_exponent(d.m, d.n, acc, (int)threadIdx.x, 64, f);
+  if (threadIdx.x == 0) mats[i].pad_e = x;
+}
 
 // per matrix: add its slots in chunk order, normalise, write the typed result
 __global__ void batched_finish_kernel(int kind, const BatchMatrix *__restrict__ mats, int count,
@@ -28,6 +52,14 @@ __global__ void batched_finish_kernel(int kind, const BatchMatrix *__restrict__ 
     for (int q = 2; q <= d.n - d.m; ++q) {
       dd_div_d(rh, rl, (double)q);
       if (C == 2) dd_div_d(ih, il, (double)q);
+    }
+    if (d.pad_e != 0 && d.n > d.m) {
+      // padding rows of 2^e: the sum carries 2^(e (n-m)); removed exactly
+      const int x = -d.pad_e * (d.n - d.m);
+      rh = __builtin_ldexp(rh, x);
+      rl = __builtin_ldexp(rl, x);
+      ih = __builtin_ldexp(ih, x);
+      il = __builtin_ldexp(il, x);
     }
   }
   double h1, l1, h2, l2;
@@ -70,6 +102,11 @@ hipError_t launch_batched_bucket(const BatchLaunch &L, int i, hipStream_t s) {
 
 hipError_t launch_batched(const BatchLaunch &L, hipStream_t s) {
   hipError_t e = hipSuccess;
+  if (L.scale_pad && L.count > 0) {
+    hipLaunchKernelGGL(batched_pad_kernel, dim3(L.count), dim3(64), 0, s, L.kind,
+                       L.mats, L.count, L.data);
+    e = hipGetLastError();
+  }
   for (int i = 0; i < L.nbuckets && e == hipSuccess; ++i) e = launch_batched_bucket(L, i, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batched_finish_kernel, dim3((L.count + 255) / 256), dim3(256), 0, s, L.kind,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -21,7 +22,8 @@ struct perm_batch_plan {
   uint32_t *d_item_matrix = nullptr;
   uint32_t *d_item_chunk = nullptr;
   double *d_slots = nullptr;
-  double *d_ones = nullptr;
+  double *d_pad_rows = nullptr;  // constant rows 2^e, e in [-PAD_EXP_MAX, PAD_EXP_MAX]
+  int scale_pad = 0;             // rectangular matrices with scaled padding rows
   // the captured launch sequence for one (data, out) pair
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -45,7 +47,7 @@ void release(perm_batch_plan *p) {
   hipFree(p->d_item_matrix);
   hipFree(p->d_item_chunk);
   hipFree(p->d_slots);
-  hipFree(p->d_ones);
+  hipFree(p->d_pad_rows);
   delete p;
 }
 
@@ -105,7 +107,8 @@ BatchLaunch make_launch(const perm_batch_plan *p, const void *data, void *out) {
   L.item_matrix = p->d_item_matrix;
   L.item_chunk = p->d_item_chunk;
   L.data = data;
-  L.ones = p->d_ones;
+  L.pad_rows = p->d_pad_rows;
+  L.scale_pad = p->scale_pad;
   L.slots = p->d_slots;
   L.buckets = p->buckets.data();
   L.nbuckets = (int)p->buckets.size();
@@ -181,7 +184,7 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
                            perm_out ot, perm_algo algo, uint32_t flags, perm_batch_plan **plan) {
   if (!plan) return PERM_E_INVALID;
   *plan = nullptr;
-  if (flags & ~PERM_BATCH_AUTOTUNE) return PERM_E_INVALID;
+  if (flags & ~(PERM_BATCH_AUTOTUNE | PERM_FLAG_PAD_ONES)) return PERM_E_INVALID;
   if (count < 0 || (count > 0 && (!hM || !hN || !hOffset || !hLd))) return PERM_E_INVALID;
   int kind = 0;
   int rc = engine_kind_for(dt, ot, kind);
@@ -203,6 +206,8 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
   p->kind = kind;
   p->ot = ot;
   p->autotune = (flags & PERM_BATCH_AUTOTUNE) != 0;
+  for (int i = 0; i < count && !(flags & PERM_FLAG_PAD_ONES); ++i)
+    if (hM[i] > 0 && hM[i] < hN[i]) p->scale_pad = 1;
   // descriptors and slots
   std::vector<BatchMatrix> mats(count);
   uint64_t slot = 0;
@@ -260,15 +265,15 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
     }
     p->buckets.push_back(bk);
   }
-  std::vector<double> ones(2 * BATCH_MAX_N);
-  for (int j = 0; j < BATCH_MAX_N; ++j) {
-    const int C = kind == ENGINE_CPLX ? 2 : 1;
-    ones[C * j] = 1.0;
-    if (C == 2) ones[2 * j + 1] = 0.0;
-  }
+  // padding rows: row e + PAD_EXP_MAX holds 2^e (complex: (2^e, 0))
+  const int Cp = kind == ENGINE_CPLX ? 2 : 1;
+  std::vector<double> pad_rows((size_t)(2 * PAD_EXP_MAX + 1) * BATCH_MAX_N * Cp, 0.0);
+  for (int e = -PAD_EXP_MAX; e <= PAD_EXP_MAX; ++e)
+    for (int j = 0; j < BATCH_MAX_N; ++j)
+      pad_rows[((size_t)(e + PAD_EXP_MAX) * BATCH_MAX_N + j) * Cp] = std::ldexp(1.0, e);
   const size_t C = kind == ENGINE_CPLX ? 2 : 1;
   if ((rc = upload(&p->d_mats, mats)) || (rc = upload(&p->d_item_matrix, item_matrix)) ||
-      (rc = upload(&p->d_item_chunk, item_chunk)) || (rc = upload(&p->d_ones, ones))) {
+      (rc = upload(&p->d_item_chunk, item_chunk)) || (rc = upload(&p->d_pad_rows, pad_rows))) {
     release(p);
     return rc;
   }

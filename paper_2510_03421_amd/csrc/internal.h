@@ -79,8 +79,13 @@ struct BatchMatrix {
   int32_t b;
   uint32_t nchunks;
   uint32_t first_slot;
-  uint32_t pad_;
+  int32_t pad_e;  // padding rows hold 2^pad_e (set on the device for m < n; 0: ones)
 };
+
+// Padding exponents of the rectangular Glynn sum are clamped to this range
+// (any nonzero padding value gives the same permanent; the range only bounds
+// the conditioning it buys).
+#define PAD_EXP_MAX 200
 
 // The work items of all matrices of one order n: items [item_begin, item_end)
 // of the item list, served round-robin by a persistent kernel of `grid`
@@ -95,12 +100,15 @@ struct BatchBucket {
 
 struct BatchLaunch {
   int kind;  // ENGINE_REAL or ENGINE_CPLX
-  const BatchMatrix *mats;
+  BatchMatrix *mats;  // device descriptors (pad_e is written on the device)
   int count;
   const uint32_t *item_matrix;  // work items grouped by order n
   const uint32_t *item_chunk;
   const void *data;
-  const double *ones;  // BATCH_MAX_N entries of 1 (complex: (1, 0) pairs)
+  // constant padding rows, one per exponent e in [-PAD_EXP_MAX, PAD_EXP_MAX]:
+  // row e holds BATCH_MAX_N entries 2^e (complex: (2^e, 0) pairs)
+  const double *pad_rows;
+  int scale_pad;  // 1: set each rectangular matrix's pad_e from its data first
   double *slots;
   const BatchBucket *buckets;  // host array
   int nbuckets;

@@ -3,6 +3,7 @@
 // the integer overflow pre-check.
 #include "device_common.h"
 #include "internal.h"
+#include "pad_model.h"
 
 namespace permgpu {
 namespace {
@@ -24,14 +25,13 @@ __device__ __forceinline__ void read_entry(perm_dtype dt, const void *dA, int64_
 }
 
 // Exponent e of the padding value 2^e of the floating-point Glynn sum on an
-// m x n matrix (m < n): the nearest power of two to rms(A) sqrt(m) / (n - m),
-// which keeps the padding rows' share of the column sums comparable to the
-// data's (with 1 the padding dominates and the sum cancels badly).  One
-// workgroup; the result goes to *e (0 for a zero matrix).
+// m x n matrix (m < n), chosen by pad_exponent from the data's mean square.
+// One workgroup; the result goes to *e (0 for a zero matrix).
 __global__ __launch_bounds__(kReduceThreads) void pad_scale_kernel(int m, int n, perm_dtype dt,
                                                                   const void *dA, int64_t lda,
                                                                   int tr, int *e) {
   __shared__ double sh[kReduceThreads];
+  __shared__ float f[kPadCandidates];
   double acc = 0.0;
   for (int idx = threadIdx.x; idx < m * n; idx += blockDim.x) {
     double re, im;
@@ -44,16 +44,8 @@ __global__ __launch_bounds__(kReduceThreads) void pad_scale_kernel(int m, int n,
     if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double ms = sh[0] / ((double)m * (double)n);
-    int x = 0;
-    if (ms > 0.0 && n > m) {
-      const double c = __builtin_sqrt(ms) * __builtin_sqrt((double)m) / (double)(n - m);
-      x = (int)rint(log2(c));
-      x = x < -200 ? -200 : (x > 200 ? 200 : x);
-    }
-    *e = x;
-  }
+  const int x = pad_exponent(m, n, sh[0], (int)threadIdx.x, (int)blockDim.x, f);
+  if (threadIdx.x == 0) *e = x;
 }
 
 // algo 0 (Glynn): NV = n, nbits = n-1, padded matrix a' (rows m..n-1 hold the

@@ -138,9 +138,8 @@ def test_packed_orders_strided_rectangular_and_partial_waves(cplx):
     for i, a in enumerate(mats):
         ref = complex(oracle.per_laplace(a))
         scale = float(oracle.per_laplace(np.abs(a)))
-        # rectangular Glynn padded with ones loses digits (see the per-matrix path)
-        bound = 1e-11 * scale * (1.0 if a.shape[0] == a.shape[1] else 1e3)
-        assert abs(got[i] - ref) <= bound, (i, a.shape, got[i], ref)
+        # rectangular ones pad with rows of 2^e scaled to the data, as single calls
+        assert abs(got[i] - ref) <= 1e-11 * scale, (i, a.shape, got[i], ref)
     plan.close()
 
 
@@ -185,6 +184,53 @@ def test_autotuned_packing(cplx):
     assert torch.equal(first, out_t)
     tuned.close()
     rule.close()
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_wide_rectangular_batches_scaled_and_ones_padding(cplx):
+    """Rectangular matrices with m << n on the chunked kernel (n >= 15): each
+    padding is as accurate as single calls of the same padding, rows of 2^e
+    scaled to the data keep far more digits than the printed rows of ones
+    (PERM_FLAG_PAD_ONES), and meet the 1e-11 per(|A|) criterion up to 28
+    columns (with m = 4 of 32 the padded sum's own rounding bound, far above
+    per(|A|), is the limit of any binary64 evaluation of it)."""
+    import torch
+
+    import paper_2510_03421_amd as pg
+    from paper_2510_03421_amd import _capi as C
+    shapes = [(3, 20), (5, 24), (2, 26), (8, 28), (6, 16), (16, 16), (4, 32)]
+    mats = [(workloads.complex_gauss(m, n, 7500 + n) if cplx else workloads.uniform(m, n, 7500 + n))
+            for m, n in shapes]
+    data, m, n, off, ld = pack(mats, np.complex128 if cplx else np.float64)
+    t = torch.from_numpy(data).cuda()
+    kind = "cdd" if cplx else "dd"
+    plan = pg.BatchPlan(m, n, off, ld, t.dtype, out=kind)
+    ones = pg.BatchPlan(m, n, off, ld, t.dtype, out=kind, flags=C.PERM_FLAG_PAD_ONES)
+    out, out1 = plan.new_output(), ones.new_output()
+    plan.run(t, out)
+    ones.run(t, out1)
+    got, got1 = to_values(out, kind, len(mats)), to_values(out1, kind, len(mats))
+
+    def single(a, flags):
+        v = pg.glynn(torch.from_numpy(a).cuda(), out=kind, flags=flags).value()
+        return complex(v[0] + v[1]) if not cplx else complex(v[0][0] + v[0][1], v[1][0] + v[1][1])
+
+    rel_s, rel_1 = [], []
+    for i, a in enumerate(mats):
+        ref = complex(oracle.per_laplace(a))
+        pabs = float(oracle.per_laplace(np.abs(a)))
+        e_s, e_1 = abs(got[i] - ref), abs(got1[i] - ref)
+        # the batch is as accurate as a single call of the same padding
+        assert e_s <= 10 * abs(single(a, 0) - ref) + 1e-13 * pabs, (a.shape, e_s)
+        assert e_1 <= 10 * abs(single(a, C.PERM_FLAG_PAD_ONES) - ref) + 1e-13 * pabs, (a.shape, e_1)
+        if a.shape[1] <= 28:
+            assert e_s <= 1e-11 * pabs, (a.shape, got[i], ref)
+        if a.shape[0] < a.shape[1]:
+            rel_s.append(e_s / abs(ref))
+            rel_1.append(e_1 / abs(ref))
+    assert max(rel_s) < 1e-9 and sum(rel_s) < 0.1 * sum(rel_1), (rel_s, rel_1)
+    plan.close()
+    ones.close()
 
 
 def test_large_orders_use_many_chunks():
