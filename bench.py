@@ -69,8 +69,8 @@ def cpu_baseline(a, budget_s: float = 15.0):
     oracle.per_glynn(a, nthreads=threads, k0=0, k1=k, partial=True)
     dt = time.perf_counter() - t0
     rate = k / max(dt, 1e-9)
-    k = int(min(TERMS, max(1 << 20, rate * budget_s)))
-    k = 1 << max(20, k.bit_length() - 1)
+    k = int(min(TERMS, max(1 << 24, rate * budget_s)))
+    k = max(1 << 24, (k >> 24) << 24)   # a multiple of 2^24 terms, about budget_s of work
     t0 = time.perf_counter()
     oracle.per_glynn(a, nthreads=threads, k0=0, k1=k, partial=True)
     dt = time.perf_counter() - t0
