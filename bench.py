@@ -79,6 +79,27 @@ def cpu_baseline(a, budget_s: float = 15.0):
                       f"(double-double Glynn evaluator, {dt:.1f} s)"}
 
 
+def environment():
+    """What the numbers were measured on."""
+    import platform
+
+    import torch
+
+    import paper_2510_03421_amd as pg
+    cpu = platform.processor()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"gpu": torch.cuda.get_device_name(0), "hip": torch.version.hip,
+            "torch": torch.__version__, "library_version": pg.version(),
+            "host_cpu": cpu, "host_threads": threads}
+
+
 def _terms(algo, m, n):
     from math import comb
     m, n = min(m, n), max(m, n)
@@ -443,6 +464,7 @@ def main():
         # the metric's second part: batched permanents per second (one graph
         # launch) against one perm_glynn call per matrix on a sample
         line["batched"] = batched(args, sample=2_000, emit=False)
+    line["env"] = environment()
     if not args.no_selector:
         # single permanents of mixed shapes: perm_auto against fixed algorithms
         line["selector"] = selector_stream(args, emit=False)
