@@ -175,6 +175,26 @@ int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, pe
 int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                void *dOut, uint32_t flags, void *stream);
 
+/* perm_gray_chunk -- one chunk of the Gray-code sum of perm_glynn (algo
+ * PERM_ALGO_GLYNN, square or rectangular) or of square perm_ryser (algo
+ * PERM_ALGO_RYSER): the terms with Gray index k in [c 2^B, (c+1) 2^B),
+ * B = chunk_log2, c = chunk, each scaled as the whole sum is (Sec. 1.2
+ * Eq. glynn, Eq. glynn_rectangle, Eq. ryser_square), so that the values of the
+ * 2^(nbits-B) chunks add up to the permanent (nbits = n-1 for Glynn, n for
+ * Ryser; B = nbits is the whole sum, equal to perm_glynn / perm_ryser
+ * bitwise).  Because g(c 2^B + k) = g(c 2^B) xor g(k) for k < 2^B, a chunk is
+ * the same walk over B bits from another closed-form seed: chunks can be
+ * computed on different GPUs or processes, or one after another with their
+ * values kept (resuming a long evaluation), and added in double-double.
+ * Floating-point outputs only (PERM_E_UNSUPPORTED for integer outputs, whose
+ * partial sums are not divisible by the normalisation, and for rectangular
+ * Ryser).  PERM_E_INVALID unless 1 <= B <= nbits (B = 0 when nbits = 0) and
+ * c < 2^(nbits-B); m = 0 takes B = 0, c = 0 (value 1).  Flags, limits and
+ * stream semantics as for perm_glynn / perm_ryser. */
+int perm_gray_chunk(perm_algo algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
+                    perm_out ot, void *dOut, uint32_t flags, int chunk_log2, uint64_t chunk,
+                    void *stream);
+
 /* perm_combinatoric -- the definition itself, one product per injective map
  * (Sec. 1.2, cost m n!/(n-m)!).  Limit: n!/(n-m)! <= 2^40 maps. */
 int perm_combinatoric(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,

@@ -21,7 +21,7 @@ from . import _capi as C
 from ._capi import PermError
 
 __all__ = ["glynn", "glynn_esym", "ryser", "combinatoric", "auto", "value", "PermError", "BatchPlan",
-           "glynn_batched", "select", "selector_load", "ALGORITHMS", "version",
+           "glynn_batched", "gray_chunk", "select", "selector_load", "ALGORITHMS", "version",
            "profile_enable", "profile_last_ms", "workspace_release"]
 
 ALGORITHMS = {C.PERM_ALGO_COMBINATORIC: "combinatoric", C.PERM_ALGO_RYSER: "ryser",
@@ -123,6 +123,21 @@ def glynn_esym(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Resul
     """Rectangular Glynn with the padding rows summed out: a sum over the signs
     of the m rows of e_m of the column sums (floating-point outputs)."""
     return _run(C.lib.perm_glynn_esym, a, out, flags)
+
+
+def gray_chunk(a: torch.Tensor, algo: str, chunk_log2: int, chunk: int, out: str | None = None,
+               flags: int = 0) -> Result:
+    """One chunk of the Glynn or square Ryser sum (perm_gray_chunk): the Gray
+    indices [chunk 2^chunk_log2, (chunk+1) 2^chunk_log2), scaled so that the
+    values of all chunks add up to the permanent."""
+    a, dt, lda = _matrix(a)
+    buf, kind = _out_for(dt, out, a.device)
+    m, n = a.shape
+    with torch.cuda.device(a.device):
+        C.check(C.lib.perm_gray_chunk(_ALGO_ID[algo], m, n, dt, a.data_ptr(), lda, _OUT[kind],
+                                      buf.data_ptr(), flags, int(chunk_log2), int(chunk), _stream(a)),
+                "perm_gray_chunk")
+    return Result(buf, kind)
 
 
 def combinatoric(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:

@@ -55,6 +55,8 @@ lib.perm_batch_plan_create.restype = _i32
 lib.perm_batch_plan_run.argtypes = [_p, _p, _p, _p]
 lib.perm_batch_plan_run.restype = _i32
 lib.perm_batch_plan_destroy.argtypes = [_p]
+lib.perm_gray_chunk.argtypes = [_i32, _i32, _i32, _i32, _p, _i64, _i32, _p, _u32, _i32, ctypes.c_uint64, _p]
+lib.perm_gray_chunk.restype = _i32
 lib.perm_batch_plan_packing.argtypes = [_p, _i32]
 lib.perm_batch_plan_packing.restype = _i32
 lib.perm_batch_plan_destroy.restype = _i32

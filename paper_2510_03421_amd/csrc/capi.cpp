@@ -296,10 +296,15 @@ int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out 
 // the Gray-walk path (Glynn square/rectangular, Ryser square)        //
 // ------------------------------------------------------------------ //
 int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
-             perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind) {
+             perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind, int chunk_log2,
+             uint64_t chunk) {
   // algo 0: Glynn (NV = N, nbits = N-1); algo 1: square Ryser (NV = M = N, nbits = N)
   const int nv = algo == 0 ? N : M;
-  const int nbits = algo == 0 ? N - 1 : N;
+  const int nbits_all = algo == 0 ? N - 1 : N;
+  // a chunk walks the low chunk_log2 bits from the seed of its first index
+  const int nbits = chunk_log2 < 0 ? nbits_all : chunk_log2;
+  const uint64_t k_first = chunk_log2 < 0 ? 0 : (chunk << chunk_log2);
+  const uint64_t g_start = k_first ^ (k_first >> 1);
   const int nv_max = kind == ENGINE_REAL ? ENGINE_MAX_NV_REAL
                      : kind == ENGINE_CPLX ? ENGINE_MAX_NV_CPLX
                                            : ENGINE_MAX_NV_INT;
@@ -321,7 +326,7 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
   }
   tune_record((double)bpl_run / (double)plan.blocks_per_lane);
   const int C = kind == ENGINE_CPLX ? 2 : 1;
-  const size_t tbl_n = (size_t)2 * nbits * nv * C;
+  const size_t tbl_n = (size_t)2 * nbits_all * nv * C;
   const size_t base_n = (size_t)nv * C;
   const size_t part_n = (size_t)plan.grid * 2 * C;
   const size_t bytes = sizeof(double) * (tbl_n + base_n + part_n) + 256;
@@ -338,7 +343,8 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     pad_exp = (int *)(part + part_n);
     e = launch_pad_scale(M, N, dt, dA, lda, tr, pad_exp, s);
   }
-  if (e == hipSuccess) e = launch_stage_gray(algo, M, N, dt, dA, lda, tr, tbl, base, C == 2, s, pad_exp);
+  if (e == hipSuccess)
+    e = launch_stage_gray(algo, M, N, dt, dA, lda, tr, tbl, base, C == 2, s, pad_exp, g_start);
   if (e == hipSuccess) {
     GrayWalk w;
     w.tbl = tbl;
@@ -506,6 +512,32 @@ int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, pe
   const int M = std::min(m, n), N = std::max(m, n);
   if (M == 0) return launch_write_one(ot, dOut, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
   return run_esym(M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind);
+}
+
+int perm_gray_chunk(perm_algo algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
+                    perm_out ot, void *dOut, uint32_t flags, int chunk_log2, uint64_t chunk,
+                    void *stream) {
+  int kind = 0;
+  int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
+  if (rc) return rc;
+  if (algo != PERM_ALGO_GLYNN && algo != PERM_ALGO_RYSER) return PERM_E_UNSUPPORTED;
+  if (kind == ENGINE_INT) return PERM_E_UNSUPPORTED;  // partial sums are not divisible
+  hipStream_t s = (hipStream_t)stream;
+  const int tr = m > n;
+  const int M = std::min(m, n), N = std::max(m, n);
+  if (algo == PERM_ALGO_RYSER && M != N) return PERM_E_UNSUPPORTED;
+  if (M == 0) {
+    if (chunk_log2 != 0 || chunk != 0) return PERM_E_INVALID;
+    return launch_write_one(ot, dOut, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
+  }
+  if (N > kMaxN) return PERM_E_TOO_LARGE;
+  const int nbits = algo == PERM_ALGO_GLYNN ? N - 1 : N;
+  // a chunk starts at an even index (its terms keep their signs): at least
+  // 2 indices, unless the whole walk is a single term
+  if (chunk_log2 < (nbits > 0 ? 1 : 0) || chunk_log2 > nbits) return PERM_E_INVALID;
+  if (chunk >= (1ull << (nbits - chunk_log2))) return PERM_E_INVALID;
+  return run_gray(algo == PERM_ALGO_GLYNN ? 0 : 1, M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind,
+                  chunk_log2, chunk);
 }
 
 int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,

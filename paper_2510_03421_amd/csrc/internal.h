@@ -130,7 +130,7 @@ struct Finish {
 // A^T.
 hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
                              int tr, double *tbl, double *base, int cplx, hipStream_t s,
-                             const int *pad_exp = nullptr);
+                             const int *pad_exp = nullptr, uint64_t g_start = 0);
 // The exponent of the floating-point Glynn padding value (device int *e).
 hipError_t launch_pad_scale(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
                             int *e, hipStream_t s);

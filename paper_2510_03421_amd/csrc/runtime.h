@@ -40,8 +40,11 @@ int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t 
                  perm_out ot, uint32_t flags, hipStream_t s, int &pl);
 
 // Runners on the logical M x N matrix (M <= N; tr = read A^T).
+// chunk_log2 < 0: the whole walk; else the chunk of 2^chunk_log2 Gray indices
+// starting at chunk * 2^chunk_log2 (floating-point outputs).
 int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
-             perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
+             perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind,
+             int chunk_log2 = -1, uint64_t chunk = 0);
 int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
                      perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
 int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,

@@ -54,9 +54,32 @@ __global__ __launch_bounds__(kReduceThreads) void pad_scale_kernel(int m, int n,
 // algo 1 (square Ryser): NV = m, nbits = n, base = 0, U[q]_i = a_{i, q}.
 // algo 2 (signs of the m rows only, no padding): NV = n, nbits = m-1,
 //   base_j = sum_{i<m} a_ij, U[q]_j = -2 a_{q+1, j}.
+// A chunk of the walk -- the indices K0 + k, K0 = c 2^B, k < 2^B -- is the
+// walk over the low B bits: g(K0 + k) = g(K0) xor g(k), so it starts from
+// v(K0) = base + sum over the set bits q of g_start = g(K0) of U[q], and
+// every row whose bit is set in g_start enters the table with the opposite
+// sign (the chunk walk uses the rows q < B, where only q = B-1 can be set,
+// for odd c).  g_start = 0 is the whole walk.
+__device__ __forceinline__ void update_entry(int algo, int m, perm_dtype dt, const void *dA,
+                                             int64_t lda, int tr, double pad, int q, int j,
+                                             double &re, double &im) {
+  if (algo != 1) {
+    if (q + 1 < m) {
+      read_entry(dt, dA, lda, tr, q + 1, j, re, im);
+    } else {
+      re = pad;
+      im = 0.0;
+    }
+    re *= -2.0;
+    im *= -2.0;
+  } else {
+    read_entry(dt, dA, lda, tr, j, q, re, im);
+  }
+}
+
 __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const void *dA,
                                   int64_t lda, int tr, double *tbl, double *base, int C,
-                                  const int *pad_exp) {
+                                  const int *pad_exp, uint64_t g_start) {
   const double pad = pad_exp ? __builtin_ldexp(1.0, *pad_exp) : 1.0;
   const int nv = algo == 1 ? m : n;
   const int nbits = algo == 0 ? n - 1 : (algo == 1 ? n : m - 1);
@@ -64,17 +87,10 @@ __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const v
   if (idx < nbits * nv) {
     const int q = idx / nv, j = idx % nv;
     double re, im;
-    if (algo != 1) {
-      if (q + 1 < m) {
-        read_entry(dt, dA, lda, tr, q + 1, j, re, im);
-      } else {
-        re = pad;
-        im = 0.0;
-      }
-      re *= -2.0;
-      im *= -2.0;
-    } else {
-      read_entry(dt, dA, lda, tr, j, q, re, im);
+    update_entry(algo, m, dt, dA, lda, tr, pad, q, j, re, im);
+    if ((g_start >> q) & 1u) {
+      re = -re;
+      im = -im;
     }
     double *p = tbl + (size_t)(2 * q) * nv * C + (size_t)j * C;
     double *mneg = tbl + (size_t)(2 * q + 1) * nv * C + (size_t)j * C;
@@ -91,6 +107,14 @@ __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const v
       for (int i = 0; i < (algo == 0 ? n : m); ++i) {
         double re = pad, im = 0.0;
         if (i < m) read_entry(dt, dA, lda, tr, i, idx, re, im);
+        sr += re;
+        si += im;
+      }
+    }
+    for (int q = 0; q < nbits; ++q) {
+      if ((g_start >> q) & 1u) {
+        double re, im;
+        update_entry(algo, m, dt, dA, lda, tr, pad, q, idx, re, im);
         sr += re;
         si += im;
       }
@@ -312,14 +336,14 @@ hipError_t launch_pad_scale(int m, int n, perm_dtype dt, const void *dA, int64_t
 
 hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
                              int tr, double *tbl, double *base, int cplx, hipStream_t s,
-                             const int *pad_exp) {
+                             const int *pad_exp, uint64_t g_start) {
   const int nv = algo == 1 ? m : n;
   const int nbits = algo == 0 ? n - 1 : (algo == 1 ? n : m - 1);
   int work = nbits * nv > nv ? nbits * nv : nv;
   if (work < 1) work = 1;
   const int threads = 256, blocks = (work + threads - 1) / threads;
   hipLaunchKernelGGL(stage_gray_kernel, dim3(blocks), dim3(threads), 0, s, algo, m, n, dt, dA, lda,
-                     tr, tbl, base, cplx ? 2 : 1, pad_exp);
+                     tr, tbl, base, cplx ? 2 : 1, pad_exp, g_start);
   return hipGetLastError();
 }
 
