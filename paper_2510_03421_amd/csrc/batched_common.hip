@@ -12,7 +12,7 @@ namespace {
 // pad_exponent from the matrix's mean square as for single matrices
 __global__ __launch_bounds__(64) void batched_pad_kernel(int kind, BatchMatrix *__restrict__ mats,
                                                          int count, const void *data) {
-  __shared__ float f[kPadCandidates];
+  __shared__ float f[kPadScratch];
   const int i = blockIdx.x;
   if (i >= count) return;
   const BatchMatrix d = mats[i];

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kReduceThreads) void pad_scale_kernel(int m, int n,
                                                                   const void *dA, int64_t lda,
                                                                   int tr, int *e) {
   __shared__ double sh[kReduceThreads];
-  __shared__ float f[kPadCandidates];
+  __shared__ float f[kPadScratch];
   double acc = 0.0;
   for (int idx = threadIdx.x; idx < m * n; idx += blockDim.x) {
     double re, im;
