@@ -31,7 +31,8 @@ COMMON = [
 
 def _sources():
     # the slowest translation units first, so the pool finishes early
-    order = ["gray_int", "gray_cplx", "batched_cplx", "ryser_rect", "batched_real", "gray_real"]
+    order = ["esym_int", "ryser_rect", "gray_int", "esym_cplx", "gray_cplx", "batched_cplx",
+             "batched_real", "gray_real"]
     srcs = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
     key = lambda f: (next((i for i, p in enumerate(order) if f.startswith(p)), len(order)), f)
     return sorted(srcs, key=key)

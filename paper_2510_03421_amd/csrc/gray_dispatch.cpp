@@ -83,18 +83,30 @@ hipError_t esym_launch_cplx_b(const GrayWalk &w, int grid, int block, void *part
 
 int esym_occ_int_a(int nv);
 int esym_occ_int_b(int nv);
+int esym_occ_int_c(int nv);
+int esym_occ_int_d(int nv);
+int esym_occ_int_e(int nv);
 hipError_t esym_launch_int_a(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
 hipError_t esym_launch_int_b(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+hipError_t esym_launch_int_c(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+hipError_t esym_launch_int_d(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+hipError_t esym_launch_int_e(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
 
 int esym_blocks_per_cu_int(int nv) {
   if (nv >= 1 && nv <= 24) return esym_occ_int_a(nv);
-  if (nv >= 25 && nv <= 48) return esym_occ_int_b(nv);
+  if (nv >= 25 && nv <= 32) return esym_occ_int_b(nv);
+  if (nv >= 33 && nv <= 40) return esym_occ_int_c(nv);
+  if (nv >= 41 && nv <= 44) return esym_occ_int_d(nv);
+  if (nv >= 45 && nv <= 48) return esym_occ_int_e(nv);
   return 0;
 }
 hipError_t launch_esym_int(const GrayWalk &w, int grid, int block, void *partials,
                            hipStream_t s) {
   if (w.nv >= 1 && w.nv <= 24) return esym_launch_int_a(w, grid, block, partials, s);
-  if (w.nv >= 25 && w.nv <= 48) return esym_launch_int_b(w, grid, block, partials, s);
+  if (w.nv >= 25 && w.nv <= 32) return esym_launch_int_b(w, grid, block, partials, s);
+  if (w.nv >= 33 && w.nv <= 40) return esym_launch_int_c(w, grid, block, partials, s);
+  if (w.nv >= 41 && w.nv <= 44) return esym_launch_int_d(w, grid, block, partials, s);
+  if (w.nv >= 45 && w.nv <= 48) return esym_launch_int_e(w, grid, block, partials, s);
   return hipErrorInvalidValue;
 }
 

@@ -149,3 +149,14 @@ def test_workspace_release_then_rectangular_ryser_again():
     pg.workspace_release()
     assert pg.ryser(dev(b)).value() == want
     assert run(b) == want
+
+
+@pytest.mark.parametrize("n", [20, 27, 36, 43, 47])
+def test_integer_kind_in_every_instantiation_range(n):
+    """Exact int128 results at column counts in each range of the integer
+    kernels (1..24, 25..32, 33..40, 41..44, 45..48) against the oracle."""
+    rng = np.random.default_rng(9400 + n)
+    a = rng.integers(-2, 3, size=(6, n)).astype(np.int64)
+    assert run(a) == oracle.per_laplace(a)
+    b = (rng.random((6, n)) < 0.5).astype(np.uint8)
+    assert run(b) == oracle.per_laplace(b.astype(np.int64))
