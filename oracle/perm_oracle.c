@@ -2,7 +2,7 @@
  * Reference permanents -- TEST INFRASTRUCTURE ONLY.
  *
  * Plain, slow CPU code used by the test-suite, the smoke check and the CPU
- * baseline leg of the benchmark to judge the HIP library.  The library never
+ * baseline leg of the benchmark to check the HIP library.  The library never
  * includes, links or calls anything in this directory, and this file shares no
  * code with it.
  *
