@@ -182,10 +182,57 @@ def suite(args):
                           "input_sha256_16": digest}),
               flush=True)
     pg.profile_enable(False)
+    if not args.only or "u32:chunks" in args.only.split(","):
+        chunks(args)
     if not args.no_batched:
         batched(args)
     if not args.no_selector:
         selector_stream(args)
+
+
+def chunks(args, parts_log2: int = 4):
+    """The 32 x 32 Glynn sum as 2^parts_log2 Gray-range chunks (perm_gray_chunk,
+    the per-GPU step of a sharded evaluation) against one perm_glynn call: wall
+    time of all chunks on one GPU, and the error of their double-double sum."""
+    import math as _m
+
+    import numpy as np
+    import torch
+
+    import paper_2510_03421_amd as pg
+    import workloads
+    a = torch.from_numpy(workloads.config_matrix("u32")).cuda()
+    B = 31 - parts_log2
+    reps = max(1, min(args.steps, 10))
+
+    def whole():
+        return pg.glynn(a, out="dd")
+
+    def parts():
+        return [pg.gray_chunk(a, "glynn", B, c, out="dd") for c in range(1 << parts_log2)]
+
+    for fn in (whole, parts):
+        fn()
+    torch.cuda.synchronize()
+    t = {}
+    for name, fn in (("single_call", whole), ("chunks", parts)):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        t[name] = (time.perf_counter() - t0) / reps * 1e3
+    vals = [x.value() for x in parts()]
+    total = _m.fsum([v[0] for v in vals] + [v[1] for v in vals])
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "reference_values.json")))["u32"]
+    ref = gold["value"]["hi"] + gold["value"]["lo"]
+    w = whole().value()
+    print(json.dumps({"workload": "u32_glynn_in_chunks", "chunks": 1 << parts_log2,
+                      "terms_per_chunk": 1 << B, "wall_ms_single_call": t["single_call"],
+                      "wall_ms_all_chunks": t["chunks"],
+                      "overhead": t["chunks"] / t["single_call"] - 1.0,
+                      "rel_err_vs_oracle": abs(total - ref) / abs(ref),
+                      "rel_diff_vs_single_call": abs(total - (w[0] + w[1])) / abs(ref)}),
+          flush=True)
 
 
 def batched(args, count: int = 200_000, sample: int = 20_000, emit: bool = True):
