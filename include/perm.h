@@ -126,24 +126,33 @@ int perm_workspace_release(void);
 /* Static description of a status code (never NULL). */
 const char *perm_status_string(int status);
 
-/* Measurement support.  perm_profile_enable(1) makes every later single-matrix
- * call record a pair of HIP events on its stream around its main kernel (the
- * Gray-walk engine, the rectangular Ryser walk or the combinatoric kernel);
- * perm_profile_last waits for the calling thread's most recent pair and
- * returns the kernel's duration in milliseconds.  PERM_E_INVALID if no pair
- * was recorded.  Off by default; costs two event records per call when on. */
+/* Measurement support.  perm_profile_enable(1) starts a session on the calling
+ * thread: every later single-matrix call from that thread records a pair of
+ * HIP events on its stream around its main kernel (the Gray-walk engine, the
+ * e_m walk, the rectangular Ryser walk or the combinatoric kernel), without
+ * waiting.  perm_profile_last waits for the session's most recent pair and
+ * returns the kernel's duration in milliseconds (PERM_E_INVALID if none was
+ * recorded); perm_profile_durations waits for the first min(capacity, count)
+ * pairs and writes their durations to the HOST array ms, in call order, with
+ * *count = the number of pairs recorded in the session.  perm_profile_enable(0)
+ * stops recording (the session's pairs stay readable).  Off by default; costs
+ * two event records per call when on. */
 int perm_profile_enable(int on);
 int perm_profile_last(double *ms);
+int perm_profile_durations(double *ms, int capacity, int *count);
 
 /* perm_glynn -- Glynn's formula, Sec. 1.2 Eq. glynn:
  *   per(A) = 2^-(n-1) sum_{delta in {+-1}^n, delta_1=+1} (prod delta) prod_j sum_i delta_i a_ij
  * summed in reflected Gray-code order; for m < n the matrix is padded with
  * n - m rows of ones and the sum divided by (n-m)! (Eq. glynn_filled_matrix,
  * Eq. glynn_rectangle).  With floating-point outputs the padding rows hold
- * c = 2^e instead, e = round(log2(rms(A) sqrt(m) / (n-m))) (sqrt(2m) in place
- * of sqrt(m) for complex input) computed on the device, and the sum is
- * divided by (n-m)! c^(n-m) (exact rescaling:
- * per([A; cJ]) = c^(n-m) per([A; J])); with rows of ones the padding
+ * c = 2^e instead, and the sum is divided by (n-m)! c^(n-m) (exact
+ * rescaling: per([A; cJ]) = c^(n-m) per([A; J])).  e is chosen on the device
+ * from the data's mean square s2 = sum |a_ij|^2 / n: among 21 powers of two
+ * around sqrt(s2 / (n-m)) it minimises a model of the padded sum's relative
+ * rounding error, F(c) = ln sum_t C(n-m, t) (s2 + c^2 (n-m-2t)^2)^(n/2)
+ * - (n-m) ln c (the terms' typical magnitude against the value's factor
+ * c^(n-m)); e is clamped to [-200, 200].  With rows of ones the padding
  * dominates the column sums and the sum loses most of its digits.
  * PERM_FLAG_PAD_ONES keeps the value 1.  Integer outputs always pad with
  * ones.  Cost 2^(n-1) terms of O(n), n = max(m, n).

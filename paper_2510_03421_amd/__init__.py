@@ -22,7 +22,7 @@ from ._capi import PermError
 
 __all__ = ["glynn", "glynn_esym", "ryser", "combinatoric", "auto", "value", "PermError", "BatchPlan",
            "glynn_batched", "gray_chunk", "select", "selector_load", "ALGORITHMS", "version",
-           "profile_enable", "profile_last_ms", "workspace_release"]
+           "profile_enable", "profile_last_ms", "profile_durations_ms", "workspace_release"]
 
 ALGORITHMS = {C.PERM_ALGO_COMBINATORIC: "combinatoric", C.PERM_ALGO_RYSER: "ryser",
               C.PERM_ALGO_GLYNN: "glynn", C.PERM_ALGO_GLYNN_ESYM: "glynn_esym"}
@@ -57,6 +57,17 @@ def profile_last_ms() -> float:
     ms = ctypes.c_double(0.0)
     C.check(C.lib.perm_profile_last(ctypes.byref(ms)), "perm_profile_last")
     return ms.value
+
+
+def profile_durations_ms() -> list:
+    """Main-kernel durations of every call since profile_enable(True), in
+    call order (waits for them)."""
+    count = ctypes.c_int(0)
+    C.check(C.lib.perm_profile_durations(None, 0, ctypes.byref(count)), "perm_profile_durations")
+    buf = (ctypes.c_double * max(1, count.value))()
+    C.check(C.lib.perm_profile_durations(buf, count.value, ctypes.byref(count)),
+            "perm_profile_durations")
+    return list(buf[:count.value])
 
 
 def _matrix(a: torch.Tensor):

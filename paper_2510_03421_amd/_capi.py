@@ -47,6 +47,8 @@ lib.perm_profile_enable.argtypes = [_i32]
 lib.perm_profile_enable.restype = _i32
 lib.perm_profile_last.argtypes = [ctypes.POINTER(_d)]
 lib.perm_profile_last.restype = _i32
+lib.perm_profile_durations.argtypes = [ctypes.POINTER(_d), _i32, ctypes.POINTER(_i32)]
+lib.perm_profile_durations.restype = _i32
 lib.perm_status_string.argtypes = [_i32]
 lib.perm_status_string.restype = ctypes.c_char_p
 lib.perm_batch_plan_create.argtypes = [_i32, _p, _p, _p, _p, _i32, _i32, _i32, _u32,

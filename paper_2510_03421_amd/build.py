@@ -38,13 +38,29 @@ def _sources():
     return sorted(srcs, key=key)
 
 
+def _band_units():
+    """The banded e_m objects: esym_band.inc compiled once per X(kind, m_lo,
+    m_hi) entry of esym_band_ranges.h."""
+    import re
+    text = open(os.path.join(CSRC, "esym_band_ranges.h")).read()
+    units = []
+    for k, lo, hi in re.findall(r"X\((\d+),\s*(\d+),\s*(\d+)\)", text):
+        units.append((f"esym_band_{k}_{lo}", "esym_band.inc",
+                      ["-x", "hip", f"-DESYM_KIND={k}", f"-DESYM_M_LO={lo}", f"-DESYM_M_HI={hi}"]))
+    # complex (slower) first
+    return sorted(units, key=lambda u: u[2][2] != "-DESYM_KIND=1")
+
+
 SOURCES = _sources()
 EXTRA = {f: ["-x", "hip"] for f in SOURCES if f.endswith(".cpp")}
+# (object name, source file, extra flags): banded units first, then one object per source
+UNITS = _band_units() + [(os.path.splitext(f)[0], f, EXTRA.get(f, [])) for f in SOURCES]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *COMMON, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit, verbose: bool) -> str:
+    name, src, extra = unit
+    obj = os.path.join(OBJDIR, name + ".o")
+    cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     t0 = time.time()
@@ -52,11 +68,11 @@ def _compile(src: str, verbose: bool) -> str:
     msgs = [ln for ln in (r.stdout + r.stderr).splitlines()
             if "packed-fp32-ops" not in ln and ln.strip()]
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {src}:\n" + "\n".join(msgs))
+        raise RuntimeError(f"hipcc failed on {name} ({src}):\n" + "\n".join(msgs))
     if verbose and msgs:
         print("\n".join(msgs))
     if verbose:
-        print(f"  {src}: {time.time() - t0:.1f}s", flush=True)
+        print(f"  {name}: {time.time() - t0:.1f}s", flush=True)
     return obj
 
 
@@ -71,8 +87,9 @@ def _includes(path: str, seen: set) -> set:
     return seen
 
 
-def _stale(src: str) -> bool:
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+def _stale(unit) -> bool:
+    name, src, _ = unit
+    obj = os.path.join(OBJDIR, name + ".o")
     if not os.path.exists(obj):
         return True
     path = os.path.join(CSRC, src)
@@ -81,14 +98,14 @@ def _stale(src: str) -> bool:
 
 
 def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
-    """Compile every source (or, with ``incremental``, only those older than
+    """Compile every unit (or, with ``incremental``, only those older than
     their inputs) and link ``libpermgpu.so``."""
     os.makedirs(OBJDIR, exist_ok=True)
-    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1))
-    todo = [s for s in SOURCES if not incremental or _stale(s)]
+    jobs = jobs or max(1, min(len(UNITS), os.cpu_count() or 1))
+    todo = [u for u in UNITS if not incremental or _stale(u)]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        list(ex.map(lambda s: _compile(s, verbose), todo))
-    objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        list(ex.map(lambda u: _compile(u, verbose), todo))
+    objs = [os.path.join(OBJDIR, u[0] + ".o") for u in UNITS]
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -58,22 +58,43 @@ static int ilog2(uint64_t x) {
 // optional engine-kernel timing (perm_profile_enable / perm_profile_last)  //
 // ------------------------------------------------------------------ //
 static std::atomic<int> g_profile{0};
-struct ProfileSlot {
-  hipEvent_t a = nullptr, b = nullptr;
-  bool valid = false;
+// The calling thread's event pairs: every call since the last
+// perm_profile_enable(1) records one pair; the events are reused by later
+// sessions.
+struct ProfileLog {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t used = 0;     // pairs recorded in this session
+  bool open = false;   // a begin without its end
 };
-static thread_local ProfileSlot t_prof;
+static thread_local ProfileLog t_prof;
 
 void profile_begin(hipStream_t s) {
+  t_prof.open = false;
   if (!g_profile.load()) return;
-  if (!t_prof.a) {
-    if (hipEventCreate(&t_prof.a) != hipSuccess || hipEventCreate(&t_prof.b) != hipSuccess) return;
+  if (t_prof.used == t_prof.ev.size()) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return;
+    }
+    t_prof.ev.emplace_back(a, b);
   }
-  t_prof.valid = hipEventRecord(t_prof.a, s) == hipSuccess;
+  t_prof.open = hipEventRecord(t_prof.ev[t_prof.used].first, s) == hipSuccess;
 }
 void profile_end(hipStream_t s) {
-  if (!g_profile.load() || !t_prof.valid) return;
-  t_prof.valid = hipEventRecord(t_prof.b, s) == hipSuccess;
+  if (!g_profile.load() || !t_prof.open) return;
+  t_prof.open = false;
+  if (hipEventRecord(t_prof.ev[t_prof.used].second, s) == hipSuccess) ++t_prof.used;
+}
+
+static int profile_ms(size_t i, double *ms) {
+  const auto &p = t_prof.ev[i];
+  if (hipEventSynchronize(p.second) != hipSuccess) return PERM_E_HIP;
+  float f = 0.f;
+  if (hipEventElapsedTime(&f, p.first, p.second) != hipSuccess) return PERM_E_HIP;
+  *ms = (double)f;
+  return PERM_OK;
 }
 
 // ------------------------------------------------------------------ //
@@ -96,12 +117,14 @@ int plan_gray(int kind, int nv, int nbits, GrayPlan &p) {
     case ENGINE_CPLX: bpc = gray_engine_blocks_per_cu_cplx(nv); break;
     default: bpc = gray_engine_blocks_per_cu_int(nv); break;
   }
-  return plan_gray_bpc(bpc, nbits, p);
+  // the engine walks groups of 8 steps
+  return plan_gray_bpc(bpc, nbits, p, 3);
 }
 
 // The plan for a walk whose kernel keeps `bpc` 256-thread workgroups resident
-// per compute unit.
-int plan_gray_bpc(int bpc, int nbits, GrayPlan &p) {
+// per compute unit: blocks of 2^b steps, b >= min_b (unless the walk is
+// shorter), as long as possible up to 2^12 while every lane gets two blocks.
+int plan_gray_bpc(int bpc, int nbits, GrayPlan &p, int min_b) {
   const int cus = device_cus();
   if (bpc <= 0 || cus <= 0) return PERM_E_HIP;
   const uint64_t lanes_max = pow2_floor((uint64_t)cus * (uint64_t)bpc * 256u);
@@ -113,9 +136,9 @@ int plan_gray_bpc(int bpc, int nbits, GrayPlan &p) {
     // as long as possible (up to 2^12 steps between closed-form re-seeds)
     // while every lane still gets at least two blocks
     b = nbits - lg - 1;
-    b = std::max(1, std::min(b, 12));
+    b = std::max(min_b, std::min(b, 12));
     const int bo = env_int("PERM_BLOCK_LOG2", -1);
-    if (bo >= 1) b = bo;
+    if (bo >= min_b) b = bo;
     b = std::min(b, nbits);
   }
   const uint64_t L = 1ull << (nbits - b);
@@ -132,6 +155,65 @@ int plan_gray_bpc(int bpc, int nbits, GrayPlan &p) {
   p.blocks_per_lane = bpl;
   p.block = (int)std::min<uint64_t>(256, lanes);
   p.grid = (int)(lanes / (uint64_t)p.block);
+  return PERM_OK;
+}
+
+// VALU operations of one e_m term on an n-vector (degree m): the n updates
+// and the recurrence -- its band for the exact-degree kernels, every degree
+// up to min(n, 32) plus the run-time pick of e_m for the generic ones; a
+// complex operation counts 4 (a complex multiply-add), the integer kind's
+// 128-bit multiply-add about 8.
+double esym_term_ops(int kind, int n, int m, bool band) {
+  double rec = 0.0;
+  const int mv = std::min(n, ESYM_MAX_M);
+  for (int j = 0; j < n; ++j) {
+    if (band) {
+      const int lo = std::max(1, j + 1 - (n - m)), hi = std::min(j + 1, m);
+      if (hi >= lo) rec += hi - lo + 1;
+    } else {
+      rec += std::min(j + 1, mv);
+    }
+  }
+  if (!band) rec += 2.0 * mv;
+  switch (kind) {
+    case ENGINE_CPLX: return 2.0 * n + 4.0 * rec;
+    case ENGINE_INT: return n + 8.0 * rec;
+    default: return n + rec;
+  }
+}
+
+// The e_m walk's plan: the block length 2^b that minimises the estimated
+// time, (waves per SIMD) x (blocks per lane) x (seed + 2^b terms), with the
+// seed costing seed_ops per Gray bit at or above b-1.  Short walks thus keep
+// every SIMD busy with short blocks; long ones amortise the seeds.
+int plan_esym(int bpc, int nbits, double term_ops, double seed_ops, GrayPlan &p) {
+  const int cus = device_cus();
+  if (bpc <= 0 || cus <= 0) return PERM_E_HIP;
+  const uint64_t lanes_max = pow2_floor((uint64_t)cus * (uint64_t)bpc * 256u);
+  const double simds = 4.0 * cus;
+  int best_b = 0;
+  double best = 0.0;
+  for (int b = nbits == 0 ? 0 : 1; b <= std::min(nbits, 12); ++b) {
+    const uint64_t L = 1ull << (nbits - b);
+    const uint64_t lanes = L == 1 ? 1 : std::min<uint64_t>(lanes_max, L / 2);
+    const double bpl = (double)(L / lanes);
+    const double waves = std::ceil((double)lanes / 64.0);
+    const double wps = std::ceil(waves / simds);
+    const double cost =
+        wps * bpl * ((double)(nbits - std::max(b - 1, 0)) * seed_ops + (double)(1ull << b) * term_ops);
+    if (b == (nbits == 0 ? 0 : 1) || cost <= best) {
+      best = cost;
+      best_b = b;
+    }
+  }
+  const int bo = env_int("PERM_ESYM_BLOCK_LOG2", -1);
+  if (bo >= 1 && bo <= nbits) best_b = bo;
+  const uint64_t L = 1ull << (nbits - best_b);
+  p.b = best_b;
+  p.lanes = L == 1 ? 1 : std::min<uint64_t>(lanes_max, L / 2);
+  p.blocks_per_lane = L / p.lanes;
+  p.block = (int)std::min<uint64_t>(256, p.lanes);
+  p.grid = (int)(p.lanes / (uint64_t)p.block);
   return PERM_OK;
 }
 
@@ -297,7 +379,7 @@ int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out 
 // ------------------------------------------------------------------ //
 int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
              perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind, int chunk_log2,
-             uint64_t chunk) {
+             uint64_t chunk, void *ext_scratch, size_t ext_bytes) {
   // algo 0: Glynn (NV = N, nbits = N-1); algo 1: square Ryser (NV = M = N, nbits = N)
   const int nv = algo == 0 ? N : M;
   const int nbits_all = algo == 0 ? N - 1 : N;
@@ -331,7 +413,12 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
   const size_t part_n = (size_t)plan.grid * 2 * C;
   const size_t bytes = sizeof(double) * (tbl_n + base_n + part_n) + 256;
   char *scratch = nullptr;
-  if (hipMallocAsync((void **)&scratch, bytes, s) != hipSuccess) return PERM_E_HIP;
+  if (ext_scratch) {
+    if (bytes > ext_bytes) return PERM_E_TOO_LARGE;
+    scratch = (char *)ext_scratch;
+  } else if (hipMallocAsync((void **)&scratch, bytes, s) != hipSuccess) {
+    return PERM_E_HIP;
+  }
   double *tbl = (double *)scratch;
   double *base = tbl + tbl_n;
   double *part = base + base_n;
@@ -355,10 +442,14 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     w.prod_levels = pl;
     w.blocks_per_lane = bpl_run;
     profile_begin(s);
-    switch (kind) {
-      case ENGINE_REAL: e = launch_gray_engine_real(w, plan.grid, plan.block, part, s); break;
-      case ENGINE_CPLX: e = launch_gray_engine_cplx(w, plan.grid, plan.block, part, s); break;
-      default: e = launch_gray_engine_int(w, plan.grid, plan.block, part, s); break;
+    if (nbits < 3) {
+      e = launch_gray_tiny(kind, w, part, s);
+    } else {
+      switch (kind) {
+        case ENGINE_REAL: e = launch_gray_engine_real(w, plan.grid, plan.block, part, s); break;
+        case ENGINE_CPLX: e = launch_gray_engine_cplx(w, plan.grid, plan.block, part, s); break;
+        default: e = launch_gray_engine_int(w, plan.grid, plan.block, part, s); break;
+      }
     }
     profile_end(s);
   }
@@ -369,10 +460,12 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     f.n = N;
     f.ot = ot;
     f.pad_exp = pad_exp;
-    e = launch_finish(kind, part, plan.grid, f, dOut, s);
+    e = launch_finish(kind, part, nbits < 3 ? 1 : plan.grid, f, dOut, s);
   }
-  hipError_t e2 = hipFreeAsync(scratch, s);
-  if (e == hipSuccess) e = e2;
+  if (!ext_scratch) {
+    hipError_t e2 = hipFreeAsync(scratch, s);
+    if (e == hipSuccess) e = e2;
+  }
   return e == hipSuccess ? PERM_OK : PERM_E_HIP;
 }
 
@@ -388,11 +481,18 @@ int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, p
     if (rc) return rc;
   }
   const int nv = N, nbits = M - 1;
-  const int bpc = kind == ENGINE_CPLX ? esym_blocks_per_cu_cplx(nv)
-                  : kind == ENGINE_INT ? esym_blocks_per_cu_int(nv)
-                                       : esym_blocks_per_cu_real(nv);
+  // exact-degree (banded) kernels exist for the floating-point kinds at m >= 14
+  // (PERM_ESYM_GENERIC=1 keeps the generic kernels: a cross-check of the two)
+  const int band_bpc = kind == ENGINE_INT || env_int("PERM_ESYM_GENERIC", 0) == 1
+                           ? 0
+                           : esym_band_blocks_per_cu(kind, nv, M);
+  const int bpc = band_bpc > 0            ? band_bpc
+                  : kind == ENGINE_CPLX ? esym_blocks_per_cu_cplx(nv)
+                  : kind == ENGINE_INT  ? esym_blocks_per_cu_int(nv)
+                                        : esym_blocks_per_cu_real(nv);
   GrayPlan plan;
-  int rc = plan_gray_bpc(bpc, nbits, plan);
+  int rc = plan_esym(bpc, nbits, esym_term_ops(kind, nv, M, band_bpc > 0),
+                     (double)(nv * (kind == ENGINE_CPLX ? 2 : 1)), plan);
   if (rc) return rc;
   uint64_t bpl_run = plan.blocks_per_lane;
   const double f = tune_fraction();
@@ -424,9 +524,10 @@ int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, p
     w.blocks_per_lane = bpl_run;
     w.m = M;
     profile_begin(s);
-    e = kind == ENGINE_CPLX  ? launch_esym_cplx(w, plan.grid, plan.block, part, s)
-        : kind == ENGINE_INT ? launch_esym_int(w, plan.grid, plan.block, part, s)
-                             : launch_esym_real(w, plan.grid, plan.block, part, s);
+    e = band_bpc > 0         ? launch_esym_band(kind, w, plan.grid, plan.block, part, s)
+        : kind == ENGINE_CPLX ? launch_esym_cplx(w, plan.grid, plan.block, part, s)
+        : kind == ENGINE_INT  ? launch_esym_int(w, plan.grid, plan.block, part, s)
+                              : launch_esym_real(w, plan.grid, plan.block, part, s);
     profile_end(s);
   }
   if (e == hipSuccess) {
@@ -464,16 +565,23 @@ int perm_workspace_release(void) {
 
 int perm_profile_enable(int on) {
   g_profile.store(on ? 1 : 0);
+  if (on) t_prof.used = 0;
   return PERM_OK;
 }
 
 int perm_profile_last(double *ms) {
   if (!ms) return PERM_E_INVALID;
-  if (!t_prof.valid) return PERM_E_INVALID;
-  if (hipEventSynchronize(t_prof.b) != hipSuccess) return PERM_E_HIP;
-  float f = 0.f;
-  if (hipEventElapsedTime(&f, t_prof.a, t_prof.b) != hipSuccess) return PERM_E_HIP;
-  *ms = (double)f;
+  if (t_prof.used == 0) return PERM_E_INVALID;
+  return profile_ms(t_prof.used - 1, ms);
+}
+
+int perm_profile_durations(double *ms, int capacity, int *count) {
+  if (!count || capacity < 0 || (capacity > 0 && !ms)) return PERM_E_INVALID;
+  *count = (int)t_prof.used;
+  for (size_t i = 0; i < t_prof.used && i < (size_t)capacity; ++i) {
+    int rc = profile_ms(i, &ms[i]);
+    if (rc) return rc;
+  }
   return PERM_OK;
 }
 

@@ -1,5 +1,6 @@
 // Routes a Gray-walk launch (engine or e_m form) to the translation unit that
 // instantiates its vector length.
+#include "esym_band_ranges.h"
 #include "internal.h"
 
 namespace permgpu {
@@ -107,6 +108,31 @@ hipError_t launch_esym_int(const GrayWalk &w, int grid, int block, void *partial
   if (w.nv >= 33 && w.nv <= 40) return esym_launch_int_c(w, grid, block, partials, s);
   if (w.nv >= 41 && w.nv <= 44) return esym_launch_int_d(w, grid, block, partials, s);
   if (w.nv >= 45 && w.nv <= 48) return esym_launch_int_e(w, grid, block, partials, s);
+  return hipErrorInvalidValue;
+}
+
+#define ESYM_BAND_DECL(k, lo, hi)                                                    \
+  int esym_band_occ_##k##_##lo(int nv, int m);                                       \
+  hipError_t esym_band_launch_##k##_##lo(const GrayWalk &w, int grid, int block,     \
+                                         void *partials, hipStream_t s);
+ESYM_BAND_RANGES(ESYM_BAND_DECL)
+#undef ESYM_BAND_DECL
+
+int esym_band_blocks_per_cu(int kind, int nv, int m) {
+  if (m < ESYM_BAND_MIN_M || m > nv || nv > ESYM_BAND_MAX_N) return 0;
+#define ESYM_BAND_OCC(k, lo, hi) \
+  if (kind == k && m >= lo && m <= hi) return esym_band_occ_##k##_##lo(nv, m);
+  ESYM_BAND_RANGES(ESYM_BAND_OCC)
+#undef ESYM_BAND_OCC
+  return 0;
+}
+
+hipError_t launch_esym_band(int kind, const GrayWalk &w, int grid, int block, void *partials,
+                            hipStream_t s) {
+#define ESYM_BAND_LAUNCH(k, lo, hi) \
+  if (kind == k && w.m >= lo && w.m <= hi) return esym_band_launch_##k##_##lo(w, grid, block, partials, s);
+  ESYM_BAND_RANGES(ESYM_BAND_LAUNCH)
+#undef ESYM_BAND_LAUNCH
   return hipErrorInvalidValue;
 }
 

@@ -145,6 +145,9 @@ hipError_t launch_gray_engine_cplx(const GrayWalk &w, int grid, int block, void 
 hipError_t launch_gray_engine_int(const GrayWalk &w, int grid, int block, void *partials,
                                   hipStream_t s);
 // Resident 256-thread workgroups per CU for an engine instantiation (0 = none).
+// Walks of fewer than 8 terms (w.nbits <= 2; the engine needs blocks of at
+// least 8 steps): one wave, one partial (count 1 for launch_finish).
+hipError_t launch_gray_tiny(int kind, const GrayWalk &w, void *partials, hipStream_t s);
 int gray_engine_blocks_per_cu_real(int nv);
 int gray_engine_blocks_per_cu_cplx(int nv);
 int gray_engine_blocks_per_cu_int(int nv);
@@ -162,6 +165,11 @@ hipError_t launch_esym_cplx(const GrayWalk &w, int grid, int block, void *partia
 hipError_t launch_esym_int(const GrayWalk &w, int grid, int block, void *partials,
                            hipStream_t s);
 int esym_blocks_per_cu_real(int nv);
+// Banded e_m kernels (exact degree w.m, kind ENGINE_REAL or ENGINE_CPLX):
+// resident workgroups per CU, 0 if no banded kernel exists for (nv, m).
+int esym_band_blocks_per_cu(int kind, int nv, int m);
+hipError_t launch_esym_band(int kind, const GrayWalk &w, int grid, int block, void *partials,
+                            hipStream_t s);
 int esym_blocks_per_cu_cplx(int nv);
 int esym_blocks_per_cu_int(int nv);
 

@@ -32,7 +32,9 @@ void tune_record(double ran);
 void tune_set(double f);
 double tune_ran();
 int plan_gray(int kind, int nv, int nbits, GrayPlan &p);
-int plan_gray_bpc(int bpc, int nbits, GrayPlan &p);
+int plan_gray_bpc(int bpc, int nbits, GrayPlan &p, int min_b = 1);
+double esym_term_ops(int kind, int n, int m, bool band);
+int plan_esym(int bpc, int nbits, double term_ops, double seed_ops, GrayPlan &p);
 int engine_kind_for(perm_dtype dt, perm_out ot, int &kind);
 int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,
              int &kind);
@@ -41,10 +43,13 @@ int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t 
 
 // Runners on the logical M x N matrix (M <= N; tr = read A^T).
 // chunk_log2 < 0: the whole walk; else the chunk of 2^chunk_log2 Gray indices
-// starting at chunk * 2^chunk_log2 (floating-point outputs).
+// starting at chunk * 2^chunk_log2 (floating-point outputs).  ext_scratch:
+// device memory of ext_bytes bytes for the walk's tables and partials instead
+// of a stream-ordered allocation (PERM_E_TOO_LARGE if it does not fit).
 int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
              perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind,
-             int chunk_log2 = -1, uint64_t chunk = 0);
+             int chunk_log2 = -1, uint64_t chunk = 0, void *ext_scratch = nullptr,
+             size_t ext_bytes = 0);
 int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
                      perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
 int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,

@@ -124,6 +124,78 @@ __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const v
   }
 }
 
+// Walks of fewer than 8 terms (nbits <= 2: Glynn n <= 3, square Ryser
+// n <= 2, chunks of 2 or 4 indices), which the block engine does not take.
+// One wave: lane k < 2^nbits forms v(k) = base + sum over the set bits q of
+// g(k) of U[q] column by column and multiplies the entries into its term;
+// lane 0 adds the signed terms in index order into partial slot 0 (format of
+// the engine's partials).  Integer products are exact (every |v_j| < 2^53 by
+// the pre-check) and taken modulo 2^128.
+__global__ __launch_bounds__(64) void gray_tiny_kernel(int kind, const double *tbl,
+                                                      const double *base, int nv, int nbits,
+                                                      void *partials) {
+  const int C = kind == ENGINE_CPLX ? 2 : 1;
+  const int k = threadIdx.x;
+  const int terms = 1 << nbits;
+  __shared__ double tr_[8], ti_[8];
+  __shared__ uint64_t tlo[8], thi[8];
+  if (k < terms) {
+    const uint32_t g = (uint32_t)(k ^ (k >> 1));
+    double pr = 1.0, pi = 0.0;
+    u128 pint = 1;
+    for (int j = 0; j < nv; ++j) {
+      double vr = base[(size_t)j * C], vi = C == 2 ? base[(size_t)j * C + 1] : 0.0;
+      for (int q = 0; q < nbits; ++q) {
+        if ((g >> q) & 1u) {
+          vr += tbl[(size_t)(2 * q) * nv * C + (size_t)j * C];
+          if (C == 2) vi += tbl[(size_t)(2 * q) * nv * C + (size_t)j * C + 1];
+        }
+      }
+      if (kind == ENGINE_INT) {
+        pint *= (u128)(i128)f64_to_i64_exact(vr);
+      } else if (C == 2) {
+        double cr, ci;
+        cmul(pr, pi, vr, vi, cr, ci);
+        pr = cr;
+        pi = ci;
+      } else {
+        pr *= vr;
+      }
+    }
+    if (k & 1) {
+      pr = -pr;
+      pi = -pi;
+      pint = (u128)0 - pint;
+    }
+    tr_[k] = pr;
+    ti_[k] = pi;
+    tlo[k] = (uint64_t)pint;
+    thi[k] = (uint64_t)(pint >> 64);
+  }
+  __syncthreads();
+  if (k == 0) {
+    if (kind == ENGINE_INT) {
+      u128 acc = 0;
+      for (int i = 0; i < terms; ++i) acc += ((u128)thi[i]) << 64 | tlo[i];
+      ((uint64_t *)partials)[0] = (uint64_t)acc;
+      ((uint64_t *)partials)[1] = (uint64_t)(acc >> 64);
+    } else {
+      double rh = 0.0, rl = 0.0, ih = 0.0, il = 0.0;
+      for (int i = 0; i < terms; ++i) {
+        dd_add(rh, rl, tr_[i], 0.0);
+        dd_add(ih, il, ti_[i], 0.0);
+      }
+      double *p = (double *)partials;
+      p[0] = rh;
+      p[1] = rl;
+      if (C == 2) {
+        p[2] = ih;
+        p[3] = il;
+      }
+    }
+  }
+}
+
 // ---- final reduction (one workgroup of kReduceThreads) ----
 __device__ __forceinline__ int v2_factorial(int k) {
   int v = 0;
@@ -344,6 +416,12 @@ hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *
   const int threads = 256, blocks = (work + threads - 1) / threads;
   hipLaunchKernelGGL(stage_gray_kernel, dim3(blocks), dim3(threads), 0, s, algo, m, n, dt, dA, lda,
                      tr, tbl, base, cplx ? 2 : 1, pad_exp, g_start);
+  return hipGetLastError();
+}
+
+hipError_t launch_gray_tiny(int kind, const GrayWalk &w, void *partials, hipStream_t s) {
+  hipLaunchKernelGGL(gray_tiny_kernel, dim3(1), dim3(64), 0, s, kind, w.tbl, w.base, w.nv, w.nbits,
+                     partials);
   return hipGetLastError();
 }
 

@@ -5,6 +5,13 @@ Run from the repository root:  python tests/golden/make_golden.py [names...]
 Each entry records the workload recipe (``workloads.CONFIGS``), the evaluator
 used, the value (exact integer, or double-double hi/lo) and, for floating
 point inputs, per(|A|) (the scale of the error criterion).
+
+``--second name...`` adds to existing entries the value of a second,
+independent evaluator: for the Glynn-evaluated inputs (32x32 real and complex,
+36x36 real) the double-double Ryser sum over column subsets (Sec. 1.2
+Eq. ryser_square), which shares no seeding or update step with the Glynn walk
+over row signs; the tests check that the two agree within their error bounds.
+Set ``ORACLE_THREADS`` to limit the threads used.
 """
 import json
 import os
@@ -49,18 +56,37 @@ def evaluate(name):
     return rec
 
 
-def main(names):
-    data = {}
-    if os.path.exists(OUT):
-        data = json.load(open(OUT))
+THREADS = int(os.environ.get("ORACLE_THREADS", "0"))
+
+
+def evaluate_second(name, rec):
+    """Add the double-double Ryser value of workload ``name`` to ``rec``."""
+    a = workloads.config_matrix(name)
+    t = time.time()
+    rec["value_ryser"] = dd_json(oracle.per_ryser(a, nthreads=THREADS))
+    rec["seconds_ryser"] = round(time.time() - t, 1)
+    return rec
+
+
+def _read():
+    return json.load(open(OUT)) if os.path.exists(OUT) else {}
+
+
+def main(names, second=False):
     for name in names:
         print(f"{name} ...", flush=True)
-        data[name] = evaluate(name)
-        print(json.dumps(data[name]), flush=True)
+        rec = evaluate_second(name, _read()[name]) if second else evaluate(name)
+        data = _read()  # re-read: another run may have added entries meanwhile
+        data[name] = rec
+        print(json.dumps(rec), flush=True)
         with open(OUT + ".tmp", "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
         os.replace(OUT + ".tmp", OUT)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["u12", "b16x48", "u20x40", "b28", "u32", "b30", "c32"])
+    args = sys.argv[1:]
+    if args and args[0] == "--second":
+        main(args[1:] or ["u32", "c32", "u36"], second=True)
+    else:
+        main(args or ["u12", "b16x48", "u20x40", "b28", "u32", "b30", "c32"])

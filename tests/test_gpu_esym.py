@@ -160,3 +160,74 @@ def test_integer_kind_in_every_instantiation_range(n):
     assert run(a) == oracle.per_laplace(a)
     b = (rng.random((6, n)) < 0.5).astype(np.uint8)
     assert run(b) == oracle.per_laplace(b.astype(np.int64))
+
+
+def esym_abs_sum_vec(a):
+    """esym_abs_sum for larger m, vectorised over the sign vectors."""
+    m, n = a.shape
+    tot = 0.0
+    step = 1 << 14
+    for s0 in range(0, 1 << (m - 1), step):
+        idx = np.arange(s0, min(1 << (m - 1), s0 + step))
+        d = np.ones((len(idx), m))
+        d[:, 1:] = 1 - 2 * ((idx[:, None] >> np.arange(m - 1)) & 1)
+        c = np.abs(d @ a)
+        e = np.zeros((len(idx), m + 1))
+        e[:, 0] = 1.0
+        for j in range(n):
+            e[:, 1:] = e[:, 1:] + c[:, j:j + 1] * e[:, :-1]
+        tot += e[:, m].sum()
+    return tot / 2 ** (m - 1)
+
+
+# exact-degree (banded) kernels run from m = 14 on
+BAND_ORACLE = [(14, 14), (14, 15), (14, 30), (15, 48), (16, 17), (16, 40), (17, 23), (18, 18),
+               (18, 36), (19, 20), (20, 33)]
+
+
+@pytest.mark.parametrize("m,n", BAND_ORACLE)
+def test_banded_against_oracle(m, n):
+    a = workloads.uniform(m, n, 9500 + 64 * m + n)
+    ref = oracle.per_laplace(a)
+    want = ref.hi + ref.lo
+    got = run(a)
+    bound = 8 * n * U * esym_abs_sum_vec(a) + 4 * U * abs(want)
+    assert abs(got - want) <= bound, (got, want, bound)
+    z = workloads.complex_gauss(m, n, 9700 + 64 * m + n)
+    refz = oracle.per_laplace(z)
+    wz = complex(refz.re.hi + refz.re.lo, refz.im.hi + refz.im.lo)
+    gz = run(z)
+    bz = 16 * n * U * esym_abs_sum_vec(np.abs(z)) + 4 * U * abs(wz)
+    assert abs(gz - wz) <= bz, (gz, wz, bz)
+
+
+def _generic(a, monkeypatch):
+    monkeypatch.setenv("PERM_ESYM_GENERIC", "1")
+    try:
+        return run(a)
+    finally:
+        monkeypatch.delenv("PERM_ESYM_GENERIC")
+
+
+# every banded degree m with a few vector lengths each (short walks: m <= 24)
+BAND_SWEEP = [(m, n) for m in range(14, 25) for n in sorted({m, m + 1, min(48, m + 7), 48})]
+
+
+@pytest.mark.parametrize("m,n", BAND_SWEEP)
+def test_banded_matches_generic(m, n, monkeypatch):
+    """The banded recurrence skips only degrees that cannot reach e_m, so the
+    two kernels evaluate the same terms; the sums differ by the rounding of
+    their (differently planned) accumulations only."""
+    a = workloads.uniform(m, n, 9900 + 64 * m + n)
+    got, ref = run(a), _generic(a, monkeypatch)
+    assert abs(got - ref) <= 1e-10 * abs(ref), (got, ref)
+    z = workloads.complex_gauss(m, n, 9950 + 64 * m + n)
+    gz, rz = run(z), _generic(z, monkeypatch)
+    assert abs(gz - rz) <= 1e-10 * abs(rz), (gz, rz)
+
+
+@pytest.mark.parametrize("m,n", [(26, 27), (28, 48), (30, 31), (32, 32), (32, 48)])
+def test_banded_large_degrees_match_generic(m, n, monkeypatch):
+    a = workloads.uniform(m, n, 9800 + 64 * m + n)
+    got, ref = run(a), _generic(a, monkeypatch)
+    assert abs(got - ref) <= 1e-10 * abs(ref), (got, ref)

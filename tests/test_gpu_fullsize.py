@@ -100,9 +100,25 @@ def test_b28_exact_int128():
 
 
 def test_b30_exact_int128():
+    """30 x 30, density 0.15, no zero row or column: a nonzero permanent,
+    bit-exact through both formulas."""
     r = rec("b30")
+    want = ref_value(r)
+    assert want > 0
     b = dev(workloads.config_matrix("b30"))
-    assert run_algo("ryser", b) == ref_value(r)
+    assert run_algo("ryser", b) == want
+    assert run_algo("glynn", b) == want
+    assert run_algo("ryser", dev(np.ascontiguousarray(workloads.config_matrix("b30").T))) == want
+
+
+def test_b30z_zero_row():
+    """The same recipe with seed 3030 has an all-zero row: per = 0 exactly,
+    and the overflow pre-check takes its shortcut."""
+    a = workloads.config_matrix("b30z")
+    assert (a.sum(axis=1) == 0).any()
+    assert ref_value(rec("b30z")) == 0
+    assert run_algo("ryser", dev(a)) == 0
+    assert run_algo("glynn", dev(a)) == 0
 
 
 def test_b16x48_exact_rectangular_ryser():

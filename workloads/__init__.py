@@ -150,8 +150,14 @@ CONFIGS = {
     "b28":   dict(kind="bernoulli", m=28, n=28, p=0.5, seed=2801),
     "u20x40": dict(kind="uniform", m=20, n=40, seed=2040),
     "b16x48": dict(kind="bernoulli", m=16, n=48, p=0.3, seed=1648),
-    "b30":   dict(kind="bernoulli", m=30, n=30, p=0.15, seed=3030),
+    # 30 x 30 sparse 0/1: seed 3031 is the first from 3031 with no zero row or
+    # column; seed 3030 has an all-zero row, kept as the degenerate case
+    "b30":   dict(kind="bernoulli", m=30, n=30, p=0.15, seed=3031),
+    "b30z":  dict(kind="bernoulli", m=30, n=30, p=0.15, seed=3030),
     "u36":   dict(kind="uniform", m=36, n=36, seed=3601),
+    # compute-bound shapes of the e_m form (2^27 terms)
+    "u28x48": dict(kind="uniform", m=28, n=48, seed=2848),
+    "c28x48": dict(kind="complex", m=28, n=48, seed=2849),
 }
 
 
