@@ -160,6 +160,26 @@ int perm_profile_durations(double *ms, int capacity, int *count);
 int perm_glynn(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                void *dOut, uint32_t flags, void *stream);
 
+/* perm_glynn_noalloc -- perm_glynn for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and launch plan, hence bitwise the same
+ * result, with the walk's scratch (update table, start vector, per-workgroup
+ * partials, padding exponent) in a fixed device array of
+ * PERM_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+ * on until the process ends (its address is looked up once per device, on
+ * the first call there).  No hipMalloc, hipFree or other allocation happens
+ * in the call.  Floating-point outputs only: integer outputs return
+ * PERM_E_UNSUPPORTED (their overflow pre-check reads the matrix back through
+ * allocated memory).  A shape whose scratch exceeds the array returns
+ * PERM_E_TOO_LARGE (no admissible shape does on a device of up to 256 compute
+ * units).  Every call on one device shares that array and leaves its last
+ * contents in it, so calls that overlap on one device -- on different streams,
+ * or from different threads -- race: the caller serialises them (one stream,
+ * or events).  Other arguments, flags and limits as for perm_glynn. */
+#define PERM_NOALLOC_SCRATCH_BYTES (256u * 1024u)
+int perm_glynn_noalloc(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+                       void *dOut, uint32_t flags, void *stream);
+
 /* perm_glynn_esym -- the rectangular Glynn sum with its padding rows summed
  * out.  The n - m rows of ones that Eq. glynn_filled_matrix appends are
  * identical, and summing their signs leaves

@@ -29,12 +29,14 @@ PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN, PERM_ALGO_GLYNN_ESYM =
 PERM_FLAG_WRAP = 0x1
 PERM_FLAG_PAD_ONES = 0x2
 PERM_BATCH_AUTOTUNE = 0x4
+PERM_NOALLOC_SCRATCH_BYTES = 256 * 1024
 
 _i32, _i64, _u32, _p, _d = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, \
     ctypes.c_double
 
 _single = [_i32, _i32, _i32, _p, _i64, _i32, _p, _u32, _p]
-for _name in ("perm_glynn", "perm_ryser", "perm_combinatoric", "perm_glynn_esym"):
+for _name in ("perm_glynn", "perm_ryser", "perm_combinatoric", "perm_glynn_esym",
+              "perm_glynn_noalloc"):
     getattr(lib, _name).argtypes = _single
     getattr(lib, _name).restype = _i32
 lib.perm_auto.argtypes = _single + [_d, ctypes.POINTER(_i32)]
