@@ -96,7 +96,8 @@ typedef enum perm_algo {
   PERM_ALGO_COMBINATORIC = 0,
   PERM_ALGO_RYSER = 1,
   PERM_ALGO_GLYNN = 2,
-  PERM_ALGO_GLYNN_ESYM = 3 /* perm_glynn_esym; reported by perm_auto only */
+  PERM_ALGO_GLYNN_ESYM = 3, /* perm_glynn_esym; reported by perm_auto only */
+  PERM_ALGO_AUTO = 4        /* batch plans: the sum chosen per matrix */
 } perm_algo;
 
 /* Flags (bitwise or). */
@@ -252,31 +253,56 @@ int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out
  * hM[b] x hN[b] with hM[b] <= hN[b] <= 32, row-major with leading dimension
  * hLd[b] >= hN[b] (elements), starting at element offset hOffset[b].  The
  * shape arrays are HOST pointers, read during the call only.  dOut receives
- * `count` values of the output type, contiguous.  Supported: Glynn's formula
- * (square, and rectangular by padding) for PERM_F64 and PERM_C128 input.  The
- * padding rows of a rectangular matrix hold 2^e with e chosen on the device
- * from that matrix's data as for perm_glynn, and the result is rescaled
- * exactly; PERM_FLAG_PAD_ONES pads with rows of ones as Eq.
- * glynn_filled_matrix prints it.  A matrix with hM[b] = 0 has permanent 1.
+ * `count` values of the output type, contiguous.  All input types and output
+ * pairs of the single-matrix calls are accepted.  A matrix with hM[b] = 0 has
+ * permanent 1.
  *
- * The Gray-code terms of each matrix are cut into chunks (work items); one
- * persistent kernel per matrix order serves all items of that order, every
- * item writes its own partial slot, and one finishing kernel adds each
- * matrix's slots in a fixed order -- results are bitwise reproducible for a
- * given plan.  Orders n <= 14 run P matrices per wave instead (P a power of
- * two, 64 / P lanes per matrix, the wave's rows staged in LDS): P follows a
- * rule set by measurement (the largest P leaving every lane a term within
- * 8 KiB of LDS), or, with PERM_BATCH_AUTOTUNE, the fastest P measured on the
- * plan's own batch.  P changes how a matrix's terms are split over lanes, so
- * results of plans with different P agree to rounding, not bitwise. */
+ * Which sum serves each matrix (the plan's algo):
+ *   PERM_ALGO_GLYNN  square: Glynn's formula (Sec. 1.2 Eq. glynn);
+ *                    rectangular: the rectangular Glynn sum with its n - m
+ *                    padding rows summed out (the e_m form of
+ *                    perm_glynn_esym: the value of Eq. glynn_rectangle without
+ *                    the rounding loss of its padding), or, with
+ *                    PERM_FLAG_PAD_ONES, padded with rows of ones exactly as
+ *                    Eq. glynn_filled_matrix prints it;
+ *   PERM_ALGO_RYSER  square only: Ryser's formula (Eq. ryser_square);
+ *                    rectangular matrices give PERM_E_UNSUPPORTED;
+ *   PERM_ALGO_AUTO   per matrix: rectangular -> the e_m form; square ->
+ *                    Glynn for floating-point outputs (half of Ryser's terms),
+ *                    Ryser for integer outputs (no extra factor 2^(n-1) in its
+ *                    integer sum).
+ * Integer outputs are exact under the rules of the single-matrix calls
+ * (sums modulo 2^128, an overflow pre-check unless PERM_FLAG_WRAP).  For
+ * 0/1 input whose shapes alone prove every result fits (|per| <= n!/(n-m)!)
+ * the pre-check costs nothing; otherwise (PERM_I64 input, or 0/1 shapes near
+ * the limits) every run first checks each matrix's bounds on the device and
+ * waits for the flags (PERM_E_OVERFLOW if one may not fit; nothing is then
+ * written).
+ *
+ * Square floating-point Glynn: the Gray-code terms of each matrix are cut
+ * into chunks (work items); one persistent kernel per matrix order serves all
+ * items of that order, every item writes its own partial slot, and one
+ * finishing kernel adds each matrix's slots in a fixed order -- results are
+ * bitwise reproducible for a given plan.  Orders n <= 14 run P matrices per
+ * wave instead (P a power of two, 64 / P lanes per matrix, the wave's rows
+ * staged in LDS): P follows a rule set by measurement (the largest P leaving
+ * every lane a term within 8 KiB of LDS), or, with PERM_BATCH_AUTOTUNE, the
+ * fastest P measured on the plan's own batch.  P changes how a matrix's terms
+ * are split over lanes, so results of plans with different P agree to
+ * rounding, not bitwise.  Every other matrix (exact integers, Ryser, the e_m
+ * form) is staged: a kernel writes its update table to plan memory, and one
+ * kernel per (order, term kind) walks chunks of 128 blocks per wave with the
+ * single-matrix engine's update and products; its slots are added in chunk
+ * order as well. */
 typedef struct perm_batch_plan perm_batch_plan;
 
 /* Build a plan (descriptors, work list, scratch) for a batch of shapes.
- * algo must be PERM_ALGO_GLYNN (PERM_E_UNSUPPORTED otherwise, and for integer
- * input/output or hM[b] > hN[b]); hN[b] > 32 gives PERM_E_TOO_LARGE.  flags:
- * PERM_BATCH_AUTOTUNE and/or PERM_FLAG_PAD_ONES (other bits PERM_E_INVALID).
- * The plan is bound to
- * the current device and owns its device memory.  Synchronous. */
+ * algo: PERM_ALGO_GLYNN, PERM_ALGO_RYSER or PERM_ALGO_AUTO (PERM_E_UNSUPPORTED
+ * otherwise, for hM[b] > hN[b], and for a rectangular matrix under
+ * PERM_ALGO_RYSER); hN[b] > 32 gives PERM_E_TOO_LARGE.  flags:
+ * PERM_BATCH_AUTOTUNE, PERM_FLAG_PAD_ONES and/or PERM_FLAG_WRAP (other bits
+ * PERM_E_INVALID).  The plan is bound to the current device and owns its
+ * device memory.  Synchronous. */
 int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
                            const int64_t *hOffset, const int64_t *hLd, perm_dtype dt,
                            perm_out ot, perm_algo algo, uint32_t flags, perm_batch_plan **plan);
@@ -306,10 +332,19 @@ int perm_batch_plan_destroy(perm_batch_plan *plan);
 
 /* One-shot convenience: create a plan, launch it without graph capture, wait
  * for the stream, destroy the plan.  flags as for perm_batch_plan_create;
- * PERM_BATCH_AUTOTUNE has no effect here (nothing is timed). */
+ * PERM_BATCH_AUTOTUNE has no effect here (nothing is timed).
+ * perm_glynn_batched: algo PERM_ALGO_GLYNN (Sec. 1.2 Eq. glynn,
+ * Eq. glynn_rectangle); perm_ryser_batched: PERM_ALGO_RYSER (Eq. ryser_square,
+ * square matrices); perm_auto_batched: PERM_ALGO_AUTO. */
 int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
                        const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
                        void *dOut, uint32_t flags, void *stream);
+int perm_ryser_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
+                       const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
+                       void *dOut, uint32_t flags, void *stream);
+int perm_auto_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
+                      const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
+                      void *dOut, uint32_t flags, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Algorithm selection                                                     */

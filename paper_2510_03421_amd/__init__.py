@@ -21,12 +21,13 @@ from . import _capi as C
 from ._capi import PermError
 
 __all__ = ["glynn", "glynn_esym", "ryser", "combinatoric", "auto", "value", "PermError", "BatchPlan",
-           "glynn_batched", "gray_chunk", "select", "selector_load", "ALGORITHMS", "version",
+           "glynn_batched", "ryser_batched", "auto_batched", "gray_chunk", "select", "selector_load", "ALGORITHMS", "version",
            "profile_enable", "profile_last_ms", "profile_durations_ms", "workspace_release"]
 
 ALGORITHMS = {C.PERM_ALGO_COMBINATORIC: "combinatoric", C.PERM_ALGO_RYSER: "ryser",
               C.PERM_ALGO_GLYNN: "glynn", C.PERM_ALGO_GLYNN_ESYM: "glynn_esym"}
 _ALGO_ID = {v: k for k, v in ALGORITHMS.items()}
+_ALGO_ID["auto"] = C.PERM_ALGO_AUTO
 
 _DT = {torch.float64: C.PERM_F64, torch.complex128: C.PERM_C128, torch.int64: C.PERM_I64,
        torch.uint8: C.PERM_B8, torch.bool: C.PERM_B8}
@@ -253,19 +254,38 @@ class BatchPlan:
             pass
 
 
-def glynn_batched(data: torch.Tensor, m, n, offset, ld, out: str | None = None,
-                  flags: int = 0) -> torch.Tensor:
-    """One-shot batched Glynn (no graph capture)."""
+def _batched_once(fn, data: torch.Tensor, m, n, offset, ld, out, flags) -> torch.Tensor:
     import numpy as np
     m = np.ascontiguousarray(m, dtype=np.int32)
     n = np.ascontiguousarray(n, dtype=np.int32)
     offset = np.ascontiguousarray(offset, dtype=np.int64)
     ld = np.ascontiguousarray(ld, dtype=np.int64)
+    if data.dtype == torch.bool:
+        data = data.to(torch.uint8)
     dt = _DT[data.dtype]
     kind = out or _DEFAULT_OUT[dt]
     tdt, cnt = _OUTBUF[kind]
     res = torch.empty(len(n) * cnt, dtype=tdt, device=data.device)
-    C.check(C.lib.perm_glynn_batched(len(n), m.ctypes.data, n.ctypes.data, offset.ctypes.data,
-                                     ld.ctypes.data, dt, data.data_ptr(), _OUT[kind],
-                                     res.data_ptr(), flags, _stream(data)), "perm_glynn_batched")
+    C.check(fn(len(n), m.ctypes.data, n.ctypes.data, offset.ctypes.data, ld.ctypes.data, dt,
+               data.data_ptr(), _OUT[kind], res.data_ptr(), flags, _stream(data)), fn.__name__)
     return res
+
+
+def glynn_batched(data: torch.Tensor, m, n, offset, ld, out: str | None = None,
+                  flags: int = 0) -> torch.Tensor:
+    """One-shot batched Glynn (no graph capture): square matrices by Glynn's
+    formula, rectangular ones by the e_m form (rows of ones with
+    flags=PERM_FLAG_PAD_ONES)."""
+    return _batched_once(C.lib.perm_glynn_batched, data, m, n, offset, ld, out, flags)
+
+
+def ryser_batched(data: torch.Tensor, m, n, offset, ld, out: str | None = None,
+                  flags: int = 0) -> torch.Tensor:
+    """One-shot batched Ryser (square matrices)."""
+    return _batched_once(C.lib.perm_ryser_batched, data, m, n, offset, ld, out, flags)
+
+
+def auto_batched(data: torch.Tensor, m, n, offset, ld, out: str | None = None,
+                 flags: int = 0) -> torch.Tensor:
+    """One-shot batch with the sum chosen per matrix (perm_auto_batched)."""
+    return _batched_once(C.lib.perm_auto_batched, data, m, n, offset, ld, out, flags)

@@ -25,7 +25,8 @@ PERM_OK, PERM_E_INVALID, PERM_E_TOO_LARGE, PERM_E_OVERFLOW, PERM_E_HIP, PERM_E_U
 PERM_F64, PERM_C128, PERM_I64, PERM_B8 = 0, 1, 2, 3
 PERM_OUT_F64, PERM_OUT_C128, PERM_OUT_I64, PERM_OUT_I128, PERM_OUT_DD, PERM_OUT_CDD = \
     0, 1, 2, 3, 4, 5
-PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN, PERM_ALGO_GLYNN_ESYM = 0, 1, 2, 3
+PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN, PERM_ALGO_GLYNN_ESYM, PERM_ALGO_AUTO = \
+    0, 1, 2, 3, 4
 PERM_FLAG_WRAP = 0x1
 PERM_FLAG_PAD_ONES = 0x2
 PERM_BATCH_AUTOTUNE = 0x4
@@ -64,8 +65,9 @@ lib.perm_gray_chunk.restype = _i32
 lib.perm_batch_plan_packing.argtypes = [_p, _i32]
 lib.perm_batch_plan_packing.restype = _i32
 lib.perm_batch_plan_destroy.restype = _i32
-lib.perm_glynn_batched.argtypes = [_i32, _p, _p, _p, _p, _i32, _p, _i32, _p, _u32, _p]
-lib.perm_glynn_batched.restype = _i32
+for _name in ("perm_glynn_batched", "perm_ryser_batched", "perm_auto_batched"):
+    getattr(lib, _name).argtypes = [_i32, _p, _p, _p, _p, _i32, _p, _i32, _p, _u32, _p]
+    getattr(lib, _name).restype = _i32
 lib.perm_selector_load.argtypes = [ctypes.c_char_p]
 lib.perm_selector_load.restype = _i32
 lib.perm_select.argtypes = [_i32, _i32, _i32, _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]

@@ -51,10 +51,24 @@ def _band_units():
     return sorted(units, key=lambda u: u[2][2] != "-DESYM_KIND=1")
 
 
+def _walk_units():
+    """The staged batch walk objects: batched_walk.inc compiled once per
+    X(kind, esym, nv_lo, nv_hi) entry of batched_walk_units.h."""
+    import re
+    text = open(os.path.join(CSRC, "batched_walk_units.h")).read()
+    units = []
+    for k, e, lo, hi in re.findall(r"X\((\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", text):
+        units.append((f"batched_walk_{k}{e}_{lo}_{hi}", "batched_walk.inc",
+                      ["-x", "hip", f"-DBW_KIND={k}", f"-DBW_ESYM={e}", f"-DBW_NV_LO={lo}",
+                       f"-DBW_NV_HI={hi}"]))
+    # the exact-integer e_m units (slowest) first
+    return sorted(units, key=lambda u: not (u[2][2] == "-DBW_KIND=2" and u[2][3] == "-DBW_ESYM=1"))
+
+
 SOURCES = _sources()
 EXTRA = {f: ["-x", "hip"] for f in SOURCES if f.endswith(".cpp")}
 # (object name, source file, extra flags): banded units first, then one object per source
-UNITS = _band_units() + [(os.path.splitext(f)[0], f, EXTRA.get(f, [])) for f in SOURCES]
+UNITS = _walk_units() + _band_units() + [(os.path.splitext(f)[0], f, EXTRA.get(f, [])) for f in SOURCES]
 
 
 def _compile(unit, verbose: bool) -> str:

@@ -37,6 +37,7 @@ __global__ void batched_finish_kernel(int kind, const BatchMatrix *__restrict__ 
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const BatchMatrix d = mats[i];
+  if (d.n < 0) return;  // a staged walk writes this matrix's result
   const int C = kind == ENGINE_CPLX ? 2 : 1;
   double rh = 0, rl = 0, ih = 0, il = 0;
   if (d.n == 0) {
@@ -111,7 +112,9 @@ hipError_t launch_batched(const BatchLaunch &L, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batched_finish_kernel, dim3((L.count + 255) / 256), dim3(256), 0, s, L.kind,
                      L.mats, L.count, L.slots, L.ot, L.out);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e == hipSuccess && L.walk) e = launch_walk_batch(*L.walk, s);
+  return e;
 }
 
 }  // namespace permgpu

@@ -34,6 +34,21 @@ struct perm_batch_plan {
   // on the first run
   bool autotune = false;
   bool tuned = false;
+  // staged walks (exact-integer batches, Ryser, the e_m form of rectangular
+  // matrices)
+  perm_dtype dt = PERM_F64;
+  uint32_t flags = 0;
+  int wcount = 0;
+  std::vector<WalkBucket> wbuckets;
+  WalkDesc *d_wdescs = nullptr;
+  uint32_t *d_windex = nullptr;
+  uint32_t *d_witem_desc = nullptr;
+  uint32_t *d_witem_chunk = nullptr;
+  double *d_arena = nullptr;
+  double *d_wslots = nullptr;
+  int *d_wflags = nullptr;
+  bool int_check = false;  // run the exact-integer pre-check on the data
+  WalkLaunch wl;           // filled per run (data and output pointers)
 };
 
 namespace {
@@ -48,6 +63,13 @@ void release(perm_batch_plan *p) {
   hipFree(p->d_item_chunk);
   hipFree(p->d_slots);
   hipFree(p->d_pad_rows);
+  hipFree(p->d_wdescs);
+  hipFree(p->d_windex);
+  hipFree(p->d_witem_desc);
+  hipFree(p->d_witem_chunk);
+  hipFree(p->d_arena);
+  hipFree(p->d_wslots);
+  hipFree(p->d_wflags);
   delete p;
 }
 
@@ -114,7 +136,66 @@ BatchLaunch make_launch(const perm_batch_plan *p, const void *data, void *out) {
   L.nbuckets = (int)p->buckets.size();
   L.ot = p->ot;
   L.out = out;
+  L.walk = nullptr;
   return L;
+}
+
+// The staged walks' launch record for (data, out), kept in the plan (the
+// batch launch refers to it).
+const WalkLaunch *make_walk(perm_batch_plan *p, const void *data, void *out) {
+  if (p->wcount == 0) return nullptr;
+  WalkLaunch &w = p->wl;
+  w.kind = p->kind;
+  w.dt = p->dt;
+  w.descs = p->d_wdescs;
+  w.index = p->d_windex;
+  w.count = p->wcount;
+  w.item_desc = p->d_witem_desc;
+  w.item_chunk = p->d_witem_chunk;
+  w.data = data;
+  w.arena = p->d_arena;
+  w.slots = p->d_wslots;
+  w.buckets = p->wbuckets.data();
+  w.nbuckets = (int)p->wbuckets.size();
+  w.ot = p->ot;
+  w.out = out;
+  return &w;
+}
+
+BatchLaunch full_launch(perm_batch_plan *p, const void *data, void *out) {
+  BatchLaunch L = make_launch(p, data, out);
+  L.walk = make_walk(p, data, out);
+  return L;
+}
+
+// Exact-integer batches whose bounds the shapes alone do not settle: the
+// per-matrix pre-check on the device (product-tree depths into the staged
+// descriptors) and, unless every result may wrap, the wait for its flags.
+int batch_int_precheck(perm_batch_plan *p, const void *data, hipStream_t s) {
+  if (!p->int_check) return PERM_OK;
+  const WalkLaunch *w = make_walk(p, data, nullptr);
+  if (launch_walk_bounds(*w, p->d_wflags, (p->flags & PERM_FLAG_WRAP) != 0, s) != hipSuccess)
+    return PERM_E_HIP;
+  std::vector<int> flags(p->wcount);
+  if (hipMemcpyAsync(flags.data(), p->d_wflags, sizeof(int) * flags.size(), hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return PERM_E_HIP;
+  for (int f : flags)
+    if (f) return PERM_E_OVERFLOW;
+  return PERM_OK;
+}
+
+// log2 of an upper bound on the magnitude of the integer sum a walk forms on
+// an m x n 0/1 matrix (|per| <= n!/(n-m)! injective maps), for the shape-only
+// overflow check of 0/1 batches; `per_only` gives the bound on |per| itself.
+double b8_log2_bound(int walk, int m, int n, bool per_only) {
+  double lg = std::lgamma((double)n + 1.0) / std::log(2.0) -
+              std::lgamma((double)(n - m) + 1.0) / std::log(2.0);
+  if (per_only) return lg;
+  if (walk == WALK_GLYNN) lg += (double)(n - 1) + std::lgamma((double)(n - m) + 1.0) / std::log(2.0);
+  if (walk == WALK_ESYM) lg += (double)(m - 1);
+  return lg;
 }
 
 // Times every admissible P of each small order on the caller's data (three
@@ -184,19 +265,36 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
                            perm_out ot, perm_algo algo, uint32_t flags, perm_batch_plan **plan) {
   if (!plan) return PERM_E_INVALID;
   *plan = nullptr;
-  if (flags & ~(PERM_BATCH_AUTOTUNE | PERM_FLAG_PAD_ONES)) return PERM_E_INVALID;
+  if (flags & ~(PERM_BATCH_AUTOTUNE | PERM_FLAG_PAD_ONES | PERM_FLAG_WRAP)) return PERM_E_INVALID;
   if (count < 0 || (count > 0 && (!hM || !hN || !hOffset || !hLd))) return PERM_E_INVALID;
   int kind = 0;
   int rc = engine_kind_for(dt, ot, kind);
   if (rc) return rc;
-  if (algo != PERM_ALGO_GLYNN) return PERM_E_UNSUPPORTED;
-  if (kind == ENGINE_INT) return PERM_E_UNSUPPORTED;
+  if (algo != PERM_ALGO_GLYNN && algo != PERM_ALGO_RYSER && algo != PERM_ALGO_AUTO)
+    return PERM_E_UNSUPPORTED;
   for (int i = 0; i < count; ++i) {
     if (hM[i] < 0 || hN[i] < 0 || hOffset[i] < 0) return PERM_E_INVALID;
     if (hM[i] > 0 && hLd[i] < hN[i]) return PERM_E_INVALID;
     if (hM[i] > hN[i]) return PERM_E_UNSUPPORTED;
     if (hN[i] > BATCH_MAX_N) return PERM_E_TOO_LARGE;
+    if (algo == PERM_ALGO_RYSER && hM[i] > 0 && hM[i] < hN[i]) return PERM_E_UNSUPPORTED;
   }
+  const bool pad_ones = (flags & PERM_FLAG_PAD_ONES) != 0;
+  const bool wrap = (flags & PERM_FLAG_WRAP) != 0;
+  // Which walk serves matrix i: square floating-point Glynn (and rectangular
+  // Glynn with rows of ones) on the per-order kernels below; everything else
+  // staged: exact integers, Ryser, and the e_m form of rectangular matrices
+  // (the padding rows summed out: the same sum as Eq. glynn_rectangle, without
+  // its ill-conditioned padding).
+  auto walk_of = [&](int i) -> int {
+    const int m = hM[i], n = hN[i];
+    if (m == 0) return kind == ENGINE_INT ? WALK_GLYNN : -1;
+    if (algo == PERM_ALGO_RYSER) return WALK_RYSER;
+    if (m < n) return (algo == PERM_ALGO_GLYNN && pad_ones) ? (kind == ENGINE_INT ? WALK_GLYNN : -1)
+                                                             : WALK_ESYM;
+    if (kind != ENGINE_INT) return -1;
+    return algo == PERM_ALGO_GLYNN ? WALK_GLYNN : WALK_RYSER;
+  };
   perm_batch_plan *p = new perm_batch_plan();
   if (hipGetDevice(&p->dev) != hipSuccess) {
     delete p;
@@ -205,24 +303,60 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
   p->count = count;
   p->kind = kind;
   p->ot = ot;
+  p->dt = dt;
+  p->flags = flags;
   p->autotune = (flags & PERM_BATCH_AUTOTUNE) != 0;
-  for (int i = 0; i < count && !(flags & PERM_FLAG_PAD_ONES); ++i)
-    if (hM[i] > 0 && hM[i] < hN[i]) p->scale_pad = 1;
   // descriptors and slots
   std::vector<BatchMatrix> mats(count);
   uint64_t slot = 0;
   std::vector<std::vector<uint32_t>> by_n(BATCH_MAX_N + 1);
+  std::vector<WalkDesc> wdescs;
+  std::vector<uint32_t> windex;
+  uint64_t wslot = 0, arena = 0;
+  const int C = kind == ENGINE_CPLX ? 2 : 1;
   for (int i = 0; i < count; ++i) {
     BatchMatrix &d = mats[i];
     std::memset(&d, 0, sizeof d);
     d.offset = hOffset[i];
     d.ld = hLd[i];
+    const int walk = walk_of(i);
+    if (walk >= 0) {
+      d.n = -1;  // served by a staged walk
+      WalkDesc w;
+      std::memset(&w, 0, sizeof w);
+      w.offset = hOffset[i];
+      w.ld = hLd[i];
+      w.m = hM[i];
+      w.n = hM[i] == 0 ? 0 : hN[i];
+      w.walk = walk;
+      w.nv = w.n == 0 ? 0 : (walk == WALK_RYSER ? w.m : w.n);
+      w.nbits = w.n == 0 ? 0 : (walk == WALK_GLYNN ? w.n - 1 : (walk == WALK_RYSER ? w.n : w.m - 1));
+      w.b = w.n == 0 ? 0 : batch_block_log2(w.nbits);
+      w.pl = 3;  // 0/1 input: every chunk of 8 factors is at most 32^8
+      w.nchunks = w.n == 0 ? 0 : (uint32_t)(((1ull << (w.nbits - w.b)) + 127) / 128);
+      w.first_slot = (uint32_t)wslot;
+      w.arena = arena;
+      wslot += w.nchunks;
+      if (w.n > 0) arena += (uint64_t)(2 * w.nbits + 1) * w.nv * C;
+      if (kind == ENGINE_INT && w.n > 0) {
+        if (dt != PERM_B8) {
+          p->int_check = true;  // bounds need the data
+        } else if (!wrap) {
+          const double lim = ot == PERM_OUT_I64 ? 63.0 : 127.0;
+          if (b8_log2_bound(walk, w.m, w.n, true) >= lim || b8_log2_bound(walk, w.m, w.n, false) >= 127.0)
+            p->int_check = true;
+        }
+      }
+      windex.push_back((uint32_t)i);
+      wdescs.push_back(w);
+      continue;
+    }
     d.m = hM[i];
     d.n = hM[i] == 0 ? 0 : hN[i];  // an empty product (m = 0) has per = 1
     d.first_slot = (uint32_t)slot;
     if (d.n > 0) {
       const int nbits = d.n - 1;
-      if (d.n <= pack_max_n() && pack_for(d.n, kind == ENGINE_CPLX ? 2 : 1) > 0) {
+      if (d.n <= pack_max_n() && pack_for(d.n, C) > 0) {
         d.b = 0;  // whole matrix in one wave's lane group: one slot
         d.nchunks = 1;
       } else {
@@ -234,10 +368,12 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
       by_n[d.n].push_back((uint32_t)i);
     }
   }
-  if (slot >= (1ull << 32)) {
+  if (slot >= (1ull << 32) || wslot >= (1ull << 32)) {
     delete p;
     return PERM_E_TOO_LARGE;
   }
+  for (int i = 0; i < count && !pad_ones; ++i)
+    if (mats[i].n > 0 && mats[i].m < mats[i].n) p->scale_pad = 1;
   // work items grouped by order, one bucket (one persistent kernel) per order
   std::vector<uint32_t> item_matrix, item_chunk;
   const int cus = device_cus();
@@ -265,19 +401,55 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
     }
     p->buckets.push_back(bk);
   }
+  // staged walk items, one bucket per (term kind, order)
+  std::vector<uint32_t> witem_desc, witem_chunk;
+  for (int esym = 0; esym <= 1; ++esym)
+    for (int nv = BATCH_MAX_N; nv >= 1; --nv) {
+      WalkBucket wb;
+      wb.nv = nv;
+      wb.esym = esym;
+      wb.item_begin = (uint32_t)witem_desc.size();
+      for (size_t k = 0; k < wdescs.size(); ++k) {
+        const WalkDesc &w = wdescs[k];
+        if (w.n == 0 || w.nv != nv || (w.walk == WALK_ESYM) != (esym == 1)) continue;
+        for (uint32_t c = 0; c < w.nchunks; ++c) {
+          witem_desc.push_back((uint32_t)k);
+          witem_chunk.push_back(c);
+        }
+      }
+      wb.item_end = (uint32_t)witem_desc.size();
+      if (wb.item_end == wb.item_begin) continue;
+      const int bpc = std::max(1, walk_blocks_per_cu(kind, esym, nv));
+      const uint64_t waves = wb.item_end - wb.item_begin;
+      wb.grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * bpc, (waves + 3) / 4));
+      p->wbuckets.push_back(wb);
+    }
+  p->wcount = (int)wdescs.size();
+  if (p->wcount > 0) {
+    if ((rc = upload(&p->d_wdescs, wdescs)) || (rc = upload(&p->d_windex, windex)) ||
+        (rc = upload(&p->d_witem_desc, witem_desc)) || (rc = upload(&p->d_witem_chunk, witem_chunk))) {
+      release(p);
+      return rc;
+    }
+    if (hipMalloc((void **)&p->d_arena, sizeof(double) * std::max<uint64_t>(1, arena)) != hipSuccess ||
+        hipMalloc((void **)&p->d_wslots, sizeof(double) * 4 * std::max<uint64_t>(1, wslot)) != hipSuccess ||
+        hipMalloc((void **)&p->d_wflags, sizeof(int) * (size_t)p->wcount) != hipSuccess) {
+      release(p);
+      return PERM_E_HIP;
+    }
+  }
   // padding rows: row e + PAD_EXP_MAX holds 2^e (complex: (2^e, 0))
   const int Cp = kind == ENGINE_CPLX ? 2 : 1;
   std::vector<double> pad_rows((size_t)(2 * PAD_EXP_MAX + 1) * BATCH_MAX_N * Cp, 0.0);
   for (int e = -PAD_EXP_MAX; e <= PAD_EXP_MAX; ++e)
     for (int j = 0; j < BATCH_MAX_N; ++j)
       pad_rows[((size_t)(e + PAD_EXP_MAX) * BATCH_MAX_N + j) * Cp] = std::ldexp(1.0, e);
-  const size_t C = kind == ENGINE_CPLX ? 2 : 1;
   if ((rc = upload(&p->d_mats, mats)) || (rc = upload(&p->d_item_matrix, item_matrix)) ||
       (rc = upload(&p->d_item_chunk, item_chunk)) || (rc = upload(&p->d_pad_rows, pad_rows))) {
     release(p);
     return rc;
   }
-  if (hipMalloc((void **)&p->d_slots, sizeof(double) * 2 * C * std::max<uint64_t>(1, slot)) !=
+  if (hipMalloc((void **)&p->d_slots, sizeof(double) * 2 * (size_t)C * std::max<uint64_t>(1, slot)) !=
           hipSuccess ||
       hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     release(p);
@@ -298,6 +470,8 @@ int perm_batch_plan_run(perm_batch_plan *p, const void *dData, void *dOut, void 
     if (rc) return rc;
     p->tuned = true;
   }
+  const int prc = batch_int_precheck(p, dData, s);
+  if (prc) return prc;
   if (!p->exec || p->g_data != dData || p->g_out != dOut) {
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
@@ -305,7 +479,7 @@ int perm_batch_plan_run(perm_batch_plan *p, const void *dData, void *dOut, void 
     p->graph = nullptr;
     // capture on the plan's own stream, so that any caller stream (including
     // the default one) can launch the graph
-    const BatchLaunch L = make_launch(p, dData, dOut);
+    const BatchLaunch L = full_launch(p, dData, dOut);
     if (hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return PERM_E_HIP;
     hipError_t e = launch_batched(L, p->capture_stream);
@@ -338,23 +512,62 @@ int perm_batch_plan_destroy(perm_batch_plan *p) {
   return PERM_OK;
 }
 
-int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
-                       const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
-                       void *dOut, uint32_t flags, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// One-shot batch: create a plan, run its launch sequence without graph
+// capture, wait for the stream, destroy the plan.
+int batched_once(perm_algo algo, int count, const int32_t *hM, const int32_t *hN,
+                 const int64_t *hOffset, const int64_t *hLd, perm_dtype dt, const void *dData,
+                 perm_out ot, void *dOut, uint32_t flags, void *stream) {
   if (count > 0 && (!dOut || !dData)) return PERM_E_INVALID;
   perm_batch_plan *p = nullptr;
-  int rc = perm_batch_plan_create(count, hM, hN, hOffset, hLd, dt, ot, PERM_ALGO_GLYNN, flags, &p);
+  int rc = perm_batch_plan_create(count, hM, hN, hOffset, hLd, dt, ot, algo,
+                                  flags & ~PERM_BATCH_AUTOTUNE, &p);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if (count == 0) {
     release(p);
     return PERM_OK;
   }
-  hipError_t e = launch_batched(make_launch(p, dData, dOut), s);
+  rc = batch_int_precheck(p, dData, s);
+  if (rc) {
+    (void)hipStreamSynchronize(s);
+    release(p);
+    return rc;
+  }
+  hipError_t e = launch_batched(full_launch(p, dData, dOut), s);
   // the plan's buffers are released only after the work using them is done
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipError_t e2 = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = e2;
   release(p);
   return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int perm_glynn_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
+                       const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
+                       void *dOut, uint32_t flags, void *stream) {
+  return batched_once(PERM_ALGO_GLYNN, count, hM, hN, hOffset, hLd, dt, dData, ot, dOut, flags,
+                      stream);
+}
+
+int perm_ryser_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
+                       const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
+                       void *dOut, uint32_t flags, void *stream) {
+  return batched_once(PERM_ALGO_RYSER, count, hM, hN, hOffset, hLd, dt, dData, ot, dOut, flags,
+                      stream);
+}
+
+int perm_auto_batched(int count, const int32_t *hM, const int32_t *hN, const int64_t *hOffset,
+                      const int64_t *hLd, perm_dtype dt, const void *dData, perm_out ot,
+                      void *dOut, uint32_t flags, void *stream) {
+  return batched_once(PERM_ALGO_AUTO, count, hM, hN, hOffset, hLd, dt, dData, ot, dOut, flags,
+                      stream);
 }
 
 }  // extern "C"

@@ -114,7 +114,61 @@ struct BatchLaunch {
   int nbuckets;
   perm_out ot;
   void *out;
+  const struct WalkLaunch *walk = nullptr;  // the batch's staged walks, if any
 };
+
+// Staged batch walks (batched_walk.hip / batched_walk.inc): matrices whose
+// walk the per-order Glynn kernels above do not serve -- exact-integer
+// batches, square Ryser, and the e_m form of rectangular matrices -- have
+// their update table and start vector written to a plan-owned arena by a
+// staging kernel (the single-matrix layout: row (q, d) at
+// tbl[(2q + d) nv C + j C], d = 0 for +U[q], 1 for -U[q]; then base[nv C]),
+// and one wave walks 128 blocks of 2^b terms (one chunk) per work item.
+enum WalkType : int {
+  WALK_GLYNN = 0,  // padded with rows of ones (Eq. glynn_filled_matrix), nbits = n-1
+  WALK_RYSER = 1,  // square Ryser over column subsets (Eq. ryser_square), nbits = n
+  WALK_ESYM = 2    // e_m form over the signs of the m rows, nbits = m-1
+};
+struct WalkDesc {
+  int64_t offset, ld;  // the input matrix in the caller's buffer (elements)
+  uint64_t arena;      // first double of its table in the arena
+  int32_t m, n;        // m <= n
+  int32_t walk;        // WalkType
+  int32_t nv, nbits, b;
+  int32_t pl;          // exact-integer kind: product-tree depth (chunk products < 2^53)
+  uint32_t nchunks, first_slot;
+};
+// The walk items of one (order, term kind): items [item_begin, item_end).
+struct WalkBucket {
+  int nv;
+  int esym;  // 0: product terms (Glynn, Ryser), 1: e_m terms
+  uint32_t item_begin, item_end;
+  int grid;
+};
+struct WalkLaunch {
+  int kind;                     // ENGINE_REAL, ENGINE_CPLX or ENGINE_INT
+  perm_dtype dt;                // input element type
+  WalkDesc *descs;              // device
+  const uint32_t *index;        // device: output index of each staged matrix
+  int count;                    // staged matrices
+  const uint32_t *item_desc;    // device
+  const uint32_t *item_chunk;   // device
+  const void *data;
+  double *arena;                // device
+  void *slots;                  // device, 4 doubles per slot
+  const WalkBucket *buckets;    // host
+  int nbuckets;
+  perm_out ot;
+  void *out;
+};
+// staging, the walk kernels of every bucket, and the per-matrix finish
+hipError_t launch_walk_batch(const WalkLaunch &L, hipStream_t s);
+// exact-integer batches of PERM_I64 input: per-matrix product-tree depth into
+// descs[i].pl and an overflow flag (1: the result may not fit ot, or an exact
+// product cannot be formed) into flags[i]
+hipError_t launch_walk_bounds(const WalkLaunch &L, int *flags, int wrap, hipStream_t s);
+hipError_t launch_walk_bucket(int kind, const WalkBucket &bk, const WalkLaunch &L, hipStream_t s);
+int walk_blocks_per_cu(int kind, int esym, int nv);
 
 struct Finish {
   int mode;       // FinishMode

@@ -2,6 +2,7 @@
 // reduction with the per-algorithm normalisation, and the absolute-sum pass of
 // the integer overflow pre-check.
 #include "device_common.h"
+#include "finish_common.h"
 #include "internal.h"
 #include "pad_model.h"
 
@@ -197,32 +198,6 @@ __global__ __launch_bounds__(64) void gray_tiny_kernel(int kind, const double *t
 }
 
 // ---- final reduction (one workgroup of kReduceThreads) ----
-__device__ __forceinline__ int v2_factorial(int k) {
-  int v = 0;
-  for (int q = 2; q <= k; ++q) {
-    int x = q;
-    while ((x & 1) == 0) { ++v; x >>= 1; }
-  }
-  return v;
-}
-
-__device__ u128 inverse_mod_2_128(u128 a) {  // a odd
-  u128 x = a;  // correct to 3 bits
-  for (int i = 0; i < 6; ++i) x = x * ((u128)2 - a * x);
-  return x;
-}
-
-__device__ void write_real(perm_out ot, double hi, double lo, void *out) {
-  double h, l;
-  fast_two_sum(hi, lo, h, l);
-  if (ot == PERM_OUT_DD) {
-    ((double *)out)[0] = h;
-    ((double *)out)[1] = l;
-  } else {
-    ((double *)out)[0] = h;
-  }
-}
-
 __global__ __launch_bounds__(kReduceThreads) void finish_kernel(int kind, const void *partials,
                                                                 int count, Finish f, void *out) {
   __shared__ double sh[kReduceThreads][4];
@@ -246,33 +221,8 @@ __global__ __launch_bounds__(kReduceThreads) void finish_kernel(int kind, const 
       __syncthreads();
     }
     if (t == 0) {
-      u128 E = ((u128)si[0][1]) << 64 | si[0][0];
-      i128 per;
-      if (f.mode == FINISH_GLYNN) {
-        const int k = f.n - f.m;
-        const int v = v2_factorial(k);
-        u128 odd = 1;
-        for (int q = 2; q <= k; ++q) {
-          int x = q;
-          while ((x & 1) == 0) x >>= 1;
-          odd *= (u128)x;
-        }
-        const int K = f.n - 1 + v;
-        u128 y = K >= 128 ? 0 : (E >> K);             // (odd * per) mod 2^(128-K)
-        y = y * inverse_mod_2_128(odd);               // per mod 2^(128-K)
-        const int sh_ = K;                           // sign-extend from bit 127-K
-        per = sh_ == 0 ? (i128)y : ((i128)(y << sh_)) >> sh_;
-      } else if (f.mode == FINISH_RYSER_SQ) {
-        per = (f.n & 1) ? -(i128)E : (i128)E;
-      } else {
-        per = (i128)E;
-      }
-      if (f.ot == PERM_OUT_I64) {
-        ((int64_t *)out)[0] = (int64_t)per;
-      } else {
-        ((uint64_t *)out)[0] = (uint64_t)(u128)per;
-        ((uint64_t *)out)[1] = (uint64_t)((u128)per >> 64);
-      }
+      const u128 E = ((u128)si[0][1]) << 64 | si[0][0];
+      write_int(f.ot, int_per(E, f.mode, f.m, f.n), out, 0);
     }
     return;
   }
@@ -294,31 +244,8 @@ __global__ __launch_bounds__(kReduceThreads) void finish_kernel(int kind, const 
   }
   if (t == 0) {
     double rh = sh[0][0], rl = sh[0][1], ih = sh[0][2], il = sh[0][3];
-    if (f.mode == FINISH_GLYNN) {
-      // 2^-(n-1), and 2^(-e (n-m)) for padding rows of 2^e: exact scalings
-      const int pe = f.pad_exp ? *f.pad_exp : 0;
-      const double sc = __builtin_ldexp(1.0, -(f.n - 1) - pe * (f.n - f.m));
-      rh *= sc; rl *= sc; ih *= sc; il *= sc;            // exact
-      for (int q = 2; q <= f.n - f.m; ++q) {
-        dd_div_d(rh, rl, (double)q);
-        if (C == 2) dd_div_d(ih, il, (double)q);
-      }
-    } else if (f.mode == FINISH_RYSER_SQ && (f.n & 1)) {
-      rh = -rh; rl = -rl; ih = -ih; il = -il;
-    }
-    if (C == 1) {
-      write_real(f.ot, rh, rl, out);
-    } else {
-      double h1, l1, h2, l2;
-      fast_two_sum(rh, rl, h1, l1);
-      fast_two_sum(ih, il, h2, l2);
-      double *o = (double *)out;
-      if (f.ot == PERM_OUT_CDD) {
-        o[0] = h1; o[1] = l1; o[2] = h2; o[3] = l2;
-      } else {
-        o[0] = h1; o[1] = h2;
-      }
-    }
+    fp_per(f.mode, f.m, f.n, f.pad_exp ? *f.pad_exp : 0, C == 2, rh, rl, ih, il);
+    write_fp(f.ot, rh, rl, ih, il, out, 0);
   }
 }
 

@@ -59,9 +59,8 @@ def test_random_shapes_against_oracle(cplx):
     for i, a in enumerate(mats):
         ref = complex(oracle.per_brute(a)) if a.shape[0] else 1.0
         scale = float(oracle.per_brute(np.abs(a))) if a.shape[0] else 1.0
-        # padded rectangular Glynn is ill-conditioned; the bound covers it
-        bound = 1e-11 * scale * (1.0 if a.shape[0] == a.shape[1] else 1e3) + 1e-300
-        assert abs(got[i] - ref) <= max(bound, 64 * a.shape[1] * U * scale), (i, a.shape, got[i], ref)
+        # rectangular matrices go through the e_m form (padding summed out)
+        assert abs(got[i] - ref) <= 1e-11 * scale + 1e-300, (i, a.shape, got[i], ref)
     plan.close()
 
 
@@ -138,7 +137,7 @@ def test_packed_orders_strided_rectangular_and_partial_waves(cplx):
     for i, a in enumerate(mats):
         ref = complex(oracle.per_laplace(a))
         scale = float(oracle.per_laplace(np.abs(a)))
-        # rectangular ones pad with rows of 2^e scaled to the data, as single calls
+        # rectangular ones go through the e_m form
         assert abs(got[i] - ref) <= 1e-11 * scale, (i, a.shape, got[i], ref)
     plan.close()
 
@@ -187,13 +186,11 @@ def test_autotuned_packing(cplx):
 
 
 @pytest.mark.parametrize("cplx", [False, True])
-def test_wide_rectangular_batches_scaled_and_ones_padding(cplx):
-    """Rectangular matrices with m << n on the chunked kernel (n >= 15): each
-    padding is as accurate as single calls of the same padding, rows of 2^e
-    scaled to the data keep far more digits than the printed rows of ones
-    (PERM_FLAG_PAD_ONES), and meet the 1e-11 per(|A|) criterion up to 28
-    columns (with m = 4 of 32 the padded sum's own rounding bound, far above
-    per(|A|), is the limit of any binary64 evaluation of it)."""
+def test_wide_rectangular_batches_e_m_and_ones_padding(cplx):
+    """Rectangular matrices with m << n (n >= 15): the batch evaluates them by
+    the e_m form (the padding rows summed out), which meets the 1e-11 per(|A|)
+    criterion at every shape and keeps far more digits than the printed rows
+    of ones (PERM_FLAG_PAD_ONES, as accurate as a single padded call)."""
     import torch
 
     import paper_2510_03421_amd as pg
@@ -211,8 +208,8 @@ def test_wide_rectangular_batches_scaled_and_ones_padding(cplx):
     ones.run(t, out1)
     got, got1 = to_values(out, kind, len(mats)), to_values(out1, kind, len(mats))
 
-    def single(a, flags):
-        v = pg.glynn(torch.from_numpy(a).cuda(), out=kind, flags=flags).value()
+    def single(fn, a, flags):
+        v = fn(torch.from_numpy(a).cuda(), out=kind, flags=flags).value()
         return complex(v[0] + v[1]) if not cplx else complex(v[0][0] + v[0][1], v[1][0] + v[1][1])
 
     rel_s, rel_1 = [], []
@@ -220,15 +217,17 @@ def test_wide_rectangular_batches_scaled_and_ones_padding(cplx):
         ref = complex(oracle.per_laplace(a))
         pabs = float(oracle.per_laplace(np.abs(a)))
         e_s, e_1 = abs(got[i] - ref), abs(got1[i] - ref)
-        # the batch is as accurate as a single call of the same padding
-        assert e_s <= 10 * abs(single(a, 0) - ref) + 1e-13 * pabs, (a.shape, e_s)
-        assert e_1 <= 10 * abs(single(a, C.PERM_FLAG_PAD_ONES) - ref) + 1e-13 * pabs, (a.shape, e_1)
-        if a.shape[1] <= 28:
-            assert e_s <= 1e-11 * pabs, (a.shape, got[i], ref)
+        assert e_s <= 1e-11 * pabs, (a.shape, got[i], ref)            # every shape
+        assert e_s <= 1e-12 * abs(ref), (a.shape, e_s / abs(ref))
+        if a.shape[0] < a.shape[1]:
+            # the same e_m sum as a single perm_glynn_esym call
+            assert e_s <= 10 * abs(single(pg.glynn_esym, a, 0) - ref) + 1e-13 * abs(ref)
+        # rows of ones: as accurate as a single padded call
+        assert e_1 <= 10 * abs(single(pg.glynn, a, C.PERM_FLAG_PAD_ONES) - ref) + 1e-13 * pabs
         if a.shape[0] < a.shape[1]:
             rel_s.append(e_s / abs(ref))
             rel_1.append(e_1 / abs(ref))
-    assert max(rel_s) < 1e-9 and sum(rel_s) < 0.1 * sum(rel_1), (rel_s, rel_1)
+    assert max(rel_s) < 1e-12 and sum(rel_s) < 1e-3 * sum(rel_1), (rel_s, rel_1)
     plan.close()
     ones.close()
 
@@ -272,9 +271,14 @@ def test_empty_batch_and_errors():
         pg.BatchPlan(np.array([33], np.int32), np.array([33], np.int32), np.zeros(1, np.int64),
                      np.array([33]), torch.float64)
     assert ex.value.status == -2
-    with pytest.raises(pg.PermError) as ex:        # integer batches are not served
-        pg.BatchPlan(one, one, np.zeros(1, np.int64), np.array([3]), torch.int64)
+    with pytest.raises(pg.PermError) as ex:        # Ryser batches take square matrices
+        pg.BatchPlan(np.array([2], np.int32), one, np.zeros(1, np.int64), np.array([3]),
+                     torch.int64, algo="ryser")
     assert ex.value.status == -5
     with pytest.raises(pg.PermError) as ex:        # a flag batches do not take
-        pg.BatchPlan(one, one, np.zeros(1, np.int64), np.array([3]), torch.float64, flags=0x1)
+        pg.BatchPlan(one, one, np.zeros(1, np.int64), np.array([3]), torch.float64, flags=0x8)
     assert ex.value.status == -1
+    with pytest.raises(pg.PermError) as ex:        # no batched definition
+        pg.BatchPlan(one, one, np.zeros(1, np.int64), np.array([3]), torch.float64,
+                     algo="combinatoric")
+    assert ex.value.status == -5
