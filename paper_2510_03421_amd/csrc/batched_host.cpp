@@ -332,7 +332,10 @@ int perm_batch_plan_create(int count, const int32_t *hM, const int32_t *hN,
       w.nv = w.n == 0 ? 0 : (walk == WALK_RYSER ? w.m : w.n);
       w.nbits = w.n == 0 ? 0 : (walk == WALK_GLYNN ? w.n - 1 : (walk == WALK_RYSER ? w.n : w.m - 1));
       w.b = w.n == 0 ? 0 : batch_block_log2(w.nbits);
-      w.pl = 3;  // 0/1 input: every chunk of 8 factors is at most 32^8
+      // 0/1 input: every factor (a row or a signed column sum) is at most n
+      w.pl = int_prod_selector(std::vector<uint64_t>(
+          (size_t)std::max(1, walk == WALK_RYSER ? w.m : w.n), (uint64_t)std::max(1, w.n)));
+      w.nonneg = walk == WALK_RYSER && dt == PERM_B8;
       w.nchunks = w.n == 0 ? 0 : (uint32_t)(((1ull << (w.nbits - w.b)) + 127) / 128);
       w.first_slot = (uint32_t)wslot;
       w.arena = arena;

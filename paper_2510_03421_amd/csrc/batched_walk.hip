@@ -82,9 +82,8 @@ __global__ __launch_bounds__(64) void walk_stage_kernel(const WalkDesc *__restri
 
 // Exact-integer pre-check, one thread per staged matrix (n <= 32): the
 // factors' bounds (absolute row sums for Ryser, column sums for Glynn -- with
-// the n - m padding ones -- and the e_m form) give the product-tree depth PL,
-// the largest in {3, 2, 1, 0} whose chunks of 2^PL consecutive bounds have
-// products below 2^53 (flag if a single factor can reach 2^53); the product
+// the n - m padding ones -- and the e_m form) give the product's chunk
+// selector (flag if a single factor can reach 2^52); the product
 // of the absolute row sums bounds |per| (flag if the result, times 2^(n-1)
 // (n-m)! for Glynn or 2^(m-1) for the e_m form, may reach 2^127, or |per|
 // may reach 2^63 for 64-bit outputs; not checked under PERM_FLAG_WRAP); for
@@ -120,25 +119,27 @@ __global__ void walk_bounds_kernel(WalkDesc *descs, int count, perm_dtype dt, co
     }
     bnd[f] = s;
   }
-  const uint64_t lim = 1ull << 53;
+  // the product's chunk selector: the fewest chunks of K = ceil(nf / NCH)
+  // factors whose bound products stay below 2^52 (-1: a factor can reach it)
+  const uint64_t lim = 1ull << 52;
   int pl = -1;
   bool single_ok = true;
   for (int f = 0; f < nf; ++f)
     if (bnd[f] >= lim) single_ok = false;
-  if (single_ok) {
-    for (int p = 3; p >= 0 && pl < 0; --p) {
-      const int c = 1 << p;
-      bool ok = true;
-      for (int s = 0; s < nf && ok; s += c) {
-        u128 prod = 1;
-        for (int f = s; f < nf && f < s + c; ++f) {
-          prod *= (u128)bnd[f];
-          if (prod >= (u128)lim) break;
-        }
-        if (prod >= (u128)lim) ok = false;
+  for (int sel = kIntProdSelectors - 1; sel >= 0 && pl < 0 && single_ok; --sel) {
+    int nch = int_chunk_count(sel, nf);
+    if (nch > nf) nch = nf;
+    const int c = (nf + nch - 1) / nch;
+    bool ok = true;
+    for (int s0 = 0; s0 < nf && ok; s0 += c) {
+      u128 prod = 1;
+      for (int f = s0; f < nf && f < s0 + c; ++f) {
+        prod *= (u128)bnd[f];
+        if (prod >= (u128)lim) break;
       }
-      if (ok) pl = p;
+      if (prod >= (u128)lim) ok = false;
     }
+    if (ok) pl = sel;
   }
   int flag = pl < 0;
   if (!flag && !wrap) {

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <vector>
 
+#include "device_common.h"
 #include "internal.h"
 #include "runtime.h"
 
@@ -227,22 +228,25 @@ static u128_host sat_mul(u128_host a, u128_host b) {
   return a * b;
 }
 
-// Largest product-tree depth PL in {3,2,1,0} such that every chunk of 2^PL
-// consecutive factors has a bound product below 2^53; -1 if a single factor
-// can reach 2^53.
-static int product_levels(const std::vector<uint64_t> &bounds) {
-  const u128_host lim = (u128_host)1 << 53;
+// The exact-integer product's chunk selector (int_chunk_count in
+// device_common.h): the fewest chunks of K = ceil(n / NCH) consecutive
+// factors whose bound products all stay below 2^52; -1 if a single factor
+// can reach 2^52.
+int int_prod_selector(const std::vector<uint64_t> &bounds) {
+  const u128_host lim = (u128_host)1 << 52;
+  const int nv = (int)bounds.size();
   for (uint64_t b : bounds)
     if ((u128_host)b >= lim) return -1;
-  for (int pl = 3; pl >= 0; --pl) {
-    const size_t c = (size_t)1 << pl;
+  for (int sel = kIntProdSelectors - 1; sel >= 0; --sel) {
+    const int nch = std::min(int_chunk_count(sel, nv), std::max(nv, 1));
+    const int K = (nv + nch - 1) / nch;
     bool ok = true;
-    for (size_t s = 0; s < bounds.size() && ok; s += c) {
+    for (int s0 = 0; s0 < nv && ok; s0 += K) {
       u128_host prod = 1;
-      for (size_t i = s; i < std::min(bounds.size(), s + c); ++i) prod = sat_mul(prod, bounds[i]);
+      for (int i = s0; i < std::min(nv, s0 + K); ++i) prod = sat_mul(prod, bounds[i]);
       if (prod >= lim) ok = false;
     }
-    if (ok) return pl;
+    if (ok) return sel;
   }
   return 0;
 }
@@ -283,8 +287,8 @@ int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t 
     }
   }
   // Glynn and Ryser form binary64 chunk products; the e_m form only needs
-  // every column sum exact in binary64 (product_levels < 0 iff one is not)
-  pl = product_levels(algo == 1 ? rows : cols);
+  // every column sum exact in binary64 (the selector is < 0 iff one is not)
+  pl = int_prod_selector(algo == 1 ? rows : cols);
   if (pl < 0) return PERM_E_OVERFLOW;
   if (wrap) return PERM_OK;
   // log2 of an upper bound on |per(A)| <= per(|A|):
@@ -440,6 +444,8 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     w.nbits = nbits;
     w.b = plan.b;
     w.prod_levels = pl;
+    // 0/1 Ryser: row sums are never negative
+    w.nonneg = kind == ENGINE_INT && dt == PERM_B8 && algo == 1;
     w.blocks_per_lane = bpl_run;
     profile_begin(s);
     if (nbits < 3) {
@@ -521,6 +527,7 @@ int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, p
     w.nbits = nbits;
     w.b = plan.b;
     w.prod_levels = 0;
+    w.nonneg = 0;
     w.blocks_per_lane = bpl_run;
     w.m = M;
     profile_begin(s);

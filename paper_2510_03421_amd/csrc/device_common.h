@@ -155,39 +155,119 @@ __device__ __forceinline__ void cprod_chains(const T &vr, const T &vi, double &p
   }
 }
 
-// ---- exact integer products: binary64 chunks of 2^PL factors (exact because
-// the host guarantees every chunk's bound is below 2^53), then mod 2^128.
+// ---- exact integer products (modulo 2^128) -------------------------------
+// The factors are integer-valued doubles.  They are multiplied in binary64 in
+// NCH chunks of K = ceil(NV / NCH) consecutive factors; the host picks NCH so
+// that every chunk's product is below 2^52 in magnitude, so every partial
+// product is exact.  A chunk's magnitude u < 2^52 becomes a 64-bit integer by
+// adding 2^52 (the sum's significand then holds u exactly, and its exponent
+// is fixed) and subtracting the bit pattern of 2^52 -- one floating-point add
+// and one 32-bit subtract on the high word.  The magnitudes are multiplied
+// modulo 2^128 in 32-bit limbs (the first pair exactly, 52 x 52 -> 104 bits;
+// each further chunk with one row of limb products per 32-bit half of the
+// chunk), and the chunks' signs, XORed, set the sign of the term.
+// integral |x| < 2^53: split into high and low 32-bit parts exactly
 __device__ __forceinline__ int64_t f64_to_i64_exact(double x) {
-  // |x| < 2^53 and integral: split into high and low 32-bit parts exactly
   double ax = __builtin_fabs(x);
   double h = __builtin_floor(ax * 0x1p-32);
   double l = __builtin_fma(-h, 0x1p32, ax);
   uint64_t u = ((uint64_t)(uint32_t)h << 32) | (uint64_t)(uint32_t)l;
   return x < 0 ? -(int64_t)u : (int64_t)u;
 }
-template <int NV, int C, int C0, class T>
-__device__ __forceinline__ void int_chunks(const T &v, u128 &acc) {
-  if constexpr (C0 < NV) {
-    constexpr int C1 = (C0 + C < NV) ? C0 + C : NV;
-    const double x = prod_range<C0, C1>(v);
-    const u128 xi = (u128)(i128)f64_to_i64_exact(x);
-    if constexpr (C0 == 0)
-      acc = xi;
-    else
-      acc = acc * xi;
-    int_chunks<NV, C, C1>(v, acc);
+__device__ __forceinline__ uint64_t mag52(double x) {
+  const double d = __builtin_fabs(x) + 0x1p52;
+  return (uint64_t)__double_as_longlong(d) - (uint64_t)__double_as_longlong(0x1p52);
+}
+__device__ __forceinline__ uint32_t sign_word(double x) {
+  return (uint32_t)((uint64_t)__double_as_longlong(x) >> 32);  // bit 31 = sign
+}
+
+// a, b < 2^52: the exact product (< 2^104) as (lo, hi)
+__device__ __forceinline__ void mul52x52(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t x = (uint64_t)a0 * b0;
+  uint64_t y = (uint64_t)a0 * b1 + (x >> 32);
+  y = (uint64_t)a1 * b0 + y;                      // < 2^53 + 2^32
+  const uint64_t z = (uint64_t)a1 * b1 + (y >> 32);
+  lo = (x & 0xffffffffull) | (y << 32);
+  hi = z;
+}
+
+// (lo, hi) <- (lo, hi) * c modulo 2^128, c < 2^52
+__device__ __forceinline__ void mul128x52(uint64_t &lo, uint64_t &hi, uint64_t c) {
+  const uint32_t p0 = (uint32_t)lo, p1 = (uint32_t)(lo >> 32);
+  const uint32_t p2 = (uint32_t)hi, p3 = (uint32_t)(hi >> 32);
+  const uint32_t c0 = (uint32_t)c, c1 = (uint32_t)(c >> 32);
+  const uint64_t u0 = (uint64_t)p0 * c0;
+  const uint64_t u1 = (uint64_t)p1 * c0 + (u0 >> 32);
+  const uint64_t u2 = (uint64_t)p2 * c0 + (u1 >> 32);
+  const uint32_t u3 = p3 * c0 + (uint32_t)(u2 >> 32);
+  const uint64_t w1 = (uint64_t)p0 * c1 + (uint32_t)u1;
+  const uint64_t w2 = (uint64_t)p1 * c1 + (uint32_t)u2 + (w1 >> 32);
+  const uint32_t w3 = p2 * c1 + u3 + (uint32_t)(w2 >> 32);
+  lo = (u0 & 0xffffffffull) | (w1 << 32);
+  hi = (w2 & 0xffffffffull) | ((uint64_t)w3 << 32);
+}
+
+// chunk C (factors [C K, min((C+1) K, NV))) of NCH: multiply its magnitude
+// into (lo, hi) and its sign into sg
+template <int NV, int NCH, int C, class T>
+__device__ __forceinline__ void int_chunks(const T &v, uint64_t &lo, uint64_t &hi, uint32_t &sg) {
+  constexpr int K = (NV + NCH - 1) / NCH;
+  constexpr int L = C * K, R = (C + 1) * K < NV ? (C + 1) * K : NV;
+  if constexpr (L < NV) {
+    const double x = prod_range<L, R>(v);
+    const uint64_t u = mag52(x);
+    if constexpr (C == 0) {
+      lo = u;
+      hi = 0;
+      sg = sign_word(x);
+    } else {
+      if constexpr (C == 1) mul52x52(lo, u, lo, hi);
+      else mul128x52(lo, hi, u);
+      sg ^= sign_word(x);
+    }
+    int_chunks<NV, NCH, C + 1>(v, lo, hi, sg);
   }
 }
-template <int NV, class T>
-__device__ __forceinline__ u128 int_prod(const T &v, int pl) {
-  u128 acc = 0;
-  switch (pl) {
-    case 0: int_chunks<NV, 1, 0>(v, acc); break;
-    case 1: int_chunks<NV, 2, 0>(v, acc); break;
-    case 2: int_chunks<NV, 4, 0>(v, acc); break;
-    default: int_chunks<NV, 8, 0>(v, acc); break;
+
+// The chunk counts the term code is instantiated for (index = the host's
+// product selector): with K = ceil(NV / NCH) factors per chunk.
+__host__ __device__ constexpr int int_chunk_count(int sel, int nv) {
+  return sel == 0 ? nv : sel == 1 ? 8 : sel == 2 ? 6 : sel == 3 ? 4 : sel == 4 ? 3 : sel == 5 ? 2 : 1;
+}
+constexpr int kIntProdSelectors = 7;
+
+template <int NV, int NCH, class T>
+__device__ __forceinline__ void int_prod_nch(const T &v, uint64_t &lo, uint64_t &hi, uint32_t &sg) {
+  constexpr int N = NCH < NV ? NCH : NV;
+  int_chunks<NV, N, 0>(v, lo, hi, sg);
+}
+
+// acc += (-1)^NEG prod_j v_j modulo 2^128; sel picks the chunk count (uniform)
+// and nonneg skips the sign when every factor is known to be >= 0.
+template <int NV, bool NEG, class T>
+__device__ __forceinline__ void int_prod_acc(u128 &acc, const T &v, int sel, bool nonneg) {
+  uint64_t lo = 0, hi = 0;
+  uint32_t sg = 0;
+  switch (sel) {
+    case 0: int_prod_nch<NV, NV>(v, lo, hi, sg); break;
+    case 1: int_prod_nch<NV, 8>(v, lo, hi, sg); break;
+    case 2: int_prod_nch<NV, 6>(v, lo, hi, sg); break;
+    case 3: int_prod_nch<NV, 4>(v, lo, hi, sg); break;
+    case 4: int_prod_nch<NV, 3>(v, lo, hi, sg); break;
+    case 5: int_prod_nch<NV, 2>(v, lo, hi, sg); break;
+    default: int_prod_nch<NV, 1>(v, lo, hi, sg); break;
   }
-  return acc;
+  u128 m = ((u128)hi << 64) | lo;
+  if (!nonneg) {
+    // negative product: two's complement negation, (m ^ mask) - mask
+    const u128 mask = (u128)(i128)((int32_t)sg >> 31);
+    m = (m ^ mask) - mask;
+  }
+  if constexpr (NEG) acc -= m;
+  else acc += m;
 }
 
 // ---- wave-level shuffles of 64-bit and 128-bit values ----

@@ -4,7 +4,7 @@
 // Real kind: compensated (TwoSum) accumulation of plain 8-term partials, the
 // last product multiply fused with the accumulation; complex kind: complex
 // product chains, compensated real and imaginary sums; exact-integer kind:
-// binary64 chunk products (exact below 2^53) multiplied modulo 2^128.
+// binary64 chunk products (exact below 2^52) multiplied modulo 2^128.
 #pragma once
 #include "device_common.h"
 #include "internal.h"
@@ -134,7 +134,8 @@ template <int NV>
 struct Lane<NV, ENGINE_INT> {
   double v[NV];
   u128 acc;
-  int pl;
+  int pl;       // product selector (int_chunk_count)
+  bool nonneg;  // every factor >= 0 (0/1 Ryser): no sign
   __device__ __forceinline__ void zero_acc() { acc = 0; }
   __device__ __forceinline__ void load_base(const double *__restrict__ base) {
 #pragma unroll
@@ -148,8 +149,8 @@ struct Lane<NV, ENGINE_INT> {
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] += row[j];
   }
-  __device__ __forceinline__ void term_add() { acc += int_prod<NV>(v, pl); }
-  __device__ __forceinline__ void term_sub() { acc -= int_prod<NV>(v, pl); }
+  __device__ __forceinline__ void term_add() { int_prod_acc<NV, false>(acc, v, pl, nonneg); }
+  __device__ __forceinline__ void term_sub() { int_prod_acc<NV, true>(acc, v, pl, nonneg); }
   __device__ __forceinline__ void flush() {}
 };
 

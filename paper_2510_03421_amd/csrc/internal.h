@@ -46,7 +46,8 @@ struct GrayWalk {
   int nv;              // vector length
   int nbits;           // number of Gray bits (terms = 2^nbits)
   int b;               // log2 of the per-lane block length
-  int prod_levels;     // ENGINE_INT only: exact binary64 product-tree depth
+  int prod_levels;     // ENGINE_INT only: the exact product's chunk selector
+  int nonneg;          // ENGINE_INT only: every factor >= 0 (no sign to track)
   uint64_t blocks_per_lane;
   int m;               // e_m walk only: the degree (number of rows)
 };
@@ -61,7 +62,8 @@ struct RectWalk {
   const uint64_t *binom;   // C(x, t) for x, t <= 64, at [x*65 + t]
   int m, n, l, h;
   int a_lo, a_hi;
-  int prod_levels;
+  int prod_levels;  // ENGINE_INT: the exact product's chunk selector
+  int nonneg;       // ENGINE_INT: every row sum >= 0 (0/1 input)
   uint64_t total_cost;
   // Cut-down runs (timing only): each wave stops after about
   // range * cut_q / 2^32 cost units of its range, running the walks of its
@@ -135,7 +137,8 @@ struct WalkDesc {
   int32_t m, n;        // m <= n
   int32_t walk;        // WalkType
   int32_t nv, nbits, b;
-  int32_t pl;          // exact-integer kind: product-tree depth (chunk products < 2^53)
+  int32_t pl;          // exact-integer kind: the product's chunk selector
+  int32_t nonneg;      // exact-integer kind: every factor >= 0 (0/1 Ryser)
   uint32_t nchunks, first_slot;
 };
 // The walk items of one (order, term kind): items [item_begin, item_end).
@@ -163,8 +166,8 @@ struct WalkLaunch {
 };
 // staging, the walk kernels of every bucket, and the per-matrix finish
 hipError_t launch_walk_batch(const WalkLaunch &L, hipStream_t s);
-// exact-integer batches of PERM_I64 input: per-matrix product-tree depth into
-// descs[i].pl and an overflow flag (1: the result may not fit ot, or an exact
+// exact-integer batches whose bounds need the data: per-matrix product chunk
+// selector into descs[i].pl and an overflow flag (1: the result may not fit ot, or an exact
 // product cannot be formed) into flags[i]
 hipError_t launch_walk_bounds(const WalkLaunch &L, int *flags, int wrap, hipStream_t s);
 hipError_t launch_walk_bucket(int kind, const WalkBucket &bk, const WalkLaunch &L, hipStream_t s);

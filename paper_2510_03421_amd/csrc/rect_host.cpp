@@ -253,6 +253,7 @@ int run_ryser_rect(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int
     w.a_lo = cp.a_lo;
     w.a_hi = cp.a_hi;
     w.prod_levels = pl;
+    w.nonneg = kind == ENGINE_INT && dt == PERM_B8;  // 0/1 row sums are never negative
     w.total_cost = cp.total_cost;
     w.cut_q = 1ull << 32;
     const double f = tune_fraction();

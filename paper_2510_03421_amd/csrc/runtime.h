@@ -38,6 +38,7 @@ int plan_esym(int bpc, int nbits, double term_ops, double seed_ops, GrayPlan &p)
 int engine_kind_for(perm_dtype dt, perm_out ot, int &kind);
 int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,
              int &kind);
+int int_prod_selector(const std::vector<uint64_t> &bounds);
 int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
                  perm_out ot, uint32_t flags, hipStream_t s, int &pl);
 
