@@ -97,7 +97,8 @@ typedef enum perm_algo {
   PERM_ALGO_RYSER = 1,
   PERM_ALGO_GLYNN = 2,
   PERM_ALGO_GLYNN_ESYM = 3, /* perm_glynn_esym; reported by perm_auto only */
-  PERM_ALGO_AUTO = 4        /* batch plans: the sum chosen per matrix */
+  PERM_ALGO_AUTO = 4,       /* batch plans: the sum chosen per matrix */
+  PERM_ALGO_SWEEP = 5       /* perm_column_sweep */
 } perm_algo;
 
 /* Flags (bitwise or). */
@@ -224,6 +225,21 @@ int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_ou
 int perm_gray_chunk(perm_algo algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
                     perm_out ot, void *dOut, uint32_t flags, int chunk_log2, uint64_t chunk,
                     void *stream);
+
+/* perm_column_sweep -- the definition (Sec. 1.1 Eq.
+ * rectangular_permanent_definition) regrouped column by column: with g_j[R]
+ * the sum over injective maps of the row set R into columns 0..j,
+ *   g_j[R] = g_{j-1}[R] + sum_{i in R} a_ij g_{j-1}[R \ {i}],
+ * and per(A) = g_{n-1}[all rows], over the 2^m row subsets (m = min(m, n)),
+ * only the subset sizes that can still reach m at each column.  Cost about
+ * n m 2^(m-1) multiply-adds and 2 2^m states of device memory (8 bytes each,
+ * 16 for complex and integer outputs).  No computed value is ever subtracted,
+ * so a floating-point result is within about (m + n) u per(|A|) of the true
+ * value whatever the signs (the inclusion-exclusion forms can lose all digits
+ * where their terms cancel).  Integer outputs are exact modulo 2^128, with
+ * the overflow pre-check of perm_ryser.  Limit: min(m, n) <= 28. */
+int perm_column_sweep(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+                      void *dOut, uint32_t flags, void *stream);
 
 /* perm_combinatoric -- the definition itself, one product per injective map
  * (Sec. 1.2, cost m n!/(n-m)!).  Limit: n!/(n-m)! <= 2^40 maps. */

@@ -20,12 +20,13 @@ import torch
 from . import _capi as C
 from ._capi import PermError
 
-__all__ = ["glynn", "glynn_esym", "ryser", "combinatoric", "auto", "value", "PermError", "BatchPlan",
+__all__ = ["glynn", "glynn_esym", "ryser", "combinatoric", "column_sweep", "auto", "value", "PermError", "BatchPlan",
            "glynn_batched", "ryser_batched", "auto_batched", "gray_chunk", "select", "selector_load", "ALGORITHMS", "version",
            "profile_enable", "profile_last_ms", "profile_durations_ms", "workspace_release"]
 
 ALGORITHMS = {C.PERM_ALGO_COMBINATORIC: "combinatoric", C.PERM_ALGO_RYSER: "ryser",
-              C.PERM_ALGO_GLYNN: "glynn", C.PERM_ALGO_GLYNN_ESYM: "glynn_esym"}
+              C.PERM_ALGO_GLYNN: "glynn", C.PERM_ALGO_GLYNN_ESYM: "glynn_esym",
+              C.PERM_ALGO_SWEEP: "column_sweep"}
 _ALGO_ID = {v: k for k, v in ALGORITHMS.items()}
 _ALGO_ID["auto"] = C.PERM_ALGO_AUTO
 
@@ -150,6 +151,12 @@ def gray_chunk(a: torch.Tensor, algo: str, chunk_log2: int, chunk: int, out: str
                                       buf.data_ptr(), flags, int(chunk_log2), int(chunk), _stream(a)),
                 "perm_gray_chunk")
     return Result(buf, kind)
+
+
+def column_sweep(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:
+    """The definition regrouped column by column over the 2^m row subsets
+    (perm_column_sweep): no subtraction of computed values."""
+    return _run(C.lib.perm_column_sweep, a, out, flags)
 
 
 def combinatoric(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:

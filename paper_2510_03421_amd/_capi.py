@@ -25,8 +25,8 @@ PERM_OK, PERM_E_INVALID, PERM_E_TOO_LARGE, PERM_E_OVERFLOW, PERM_E_HIP, PERM_E_U
 PERM_F64, PERM_C128, PERM_I64, PERM_B8 = 0, 1, 2, 3
 PERM_OUT_F64, PERM_OUT_C128, PERM_OUT_I64, PERM_OUT_I128, PERM_OUT_DD, PERM_OUT_CDD = \
     0, 1, 2, 3, 4, 5
-PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN, PERM_ALGO_GLYNN_ESYM, PERM_ALGO_AUTO = \
-    0, 1, 2, 3, 4
+PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN, PERM_ALGO_GLYNN_ESYM, PERM_ALGO_AUTO, \
+    PERM_ALGO_SWEEP = 0, 1, 2, 3, 4, 5
 PERM_FLAG_WRAP = 0x1
 PERM_FLAG_PAD_ONES = 0x2
 PERM_BATCH_AUTOTUNE = 0x4
@@ -37,7 +37,7 @@ _i32, _i64, _u32, _p, _d = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes
 
 _single = [_i32, _i32, _i32, _p, _i64, _i32, _p, _u32, _p]
 for _name in ("perm_glynn", "perm_ryser", "perm_combinatoric", "perm_glynn_esym",
-              "perm_glynn_noalloc"):
+              "perm_glynn_noalloc", "perm_column_sweep"):
     getattr(lib, _name).argtypes = _single
     getattr(lib, _name).restype = _i32
 lib.perm_auto.argtypes = _single + [_d, ctypes.POINTER(_i32)]

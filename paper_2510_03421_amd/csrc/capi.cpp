@@ -550,6 +550,60 @@ int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, p
   return e == hipSuccess ? PERM_OK : PERM_E_HIP;
 }
 
+// ------------------------------------------------------------------ //
+// the column sweep                                                    //
+// ------------------------------------------------------------------ //
+// State updates of column j of an m-row sweep over n columns: the states of
+// the sizes in its band, each reading one entry per row in it.
+double sweep_column_work(int m, int n, int j) {
+  const int lo = std::max(0, m - (n - 1 - j)), hi = std::min(j + 1, m);
+  double w = 0.0, c = 1.0;  // c = C(m, k)
+  for (int k = 0; k <= m; ++k) {
+    if (k >= lo && k <= hi) w += c * (double)(k + 1);
+    c = c * (double)(m - k) / (double)(k + 1);
+  }
+  return w;
+}
+
+int run_sweep(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
+              void *dOut, uint32_t flags, hipStream_t s, int kind) {
+  if (M > SWEEP_MAX_M) return PERM_E_TOO_LARGE;
+  if (kind == ENGINE_INT) {
+    // the states are permanents of submatrices, kept modulo 2^128: the value
+    // is exact when |per| < 2^127 (the Ryser bound of the pre-check)
+    int pl = 0;
+    int rc = int_precheck(1, M, N, dt, dA, lda, tr, ot, flags, s, pl);
+    if (rc == PERM_E_OVERFLOW && (flags & PERM_FLAG_WRAP)) rc = PERM_OK;
+    if (rc) return rc;
+  }
+  // perm_time: the first columns holding about the requested share of the work
+  int ncols = N;
+  const double f = tune_fraction();
+  if (f < 1.0) {
+    double total = 0.0;
+    for (int j = 0; j < N; ++j) total += sweep_column_work(M, N, j);
+    double acc = 0.0;
+    ncols = 0;
+    while (ncols < N && acc < f * total) acc += sweep_column_work(M, N, ncols++);
+    ncols = std::max(ncols, 1);
+    acc = 0.0;
+    for (int j = 0; j < ncols; ++j) acc += sweep_column_work(M, N, j);
+    tune_record(acc / total);
+  } else {
+    tune_record(1.0);
+  }
+  const size_t sb = kind == ENGINE_REAL ? 8 : 16;
+  const size_t bytes = sb << M;
+  char *buf = nullptr;
+  if (hipMallocAsync((void **)&buf, 2 * bytes, s) != hipSuccess) return PERM_E_HIP;
+  profile_begin(s);
+  hipError_t e = launch_sweep(kind, M, N, dt, dA, lda, tr, buf, buf + bytes, sb, ot, dOut, s, ncols);
+  profile_end(s);
+  hipError_t e2 = hipFreeAsync(buf, s);
+  if (e == hipSuccess) e = e2;
+  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+}
+
 }  // namespace permgpu
 
 // ==================================================================== //
@@ -653,6 +707,19 @@ int perm_gray_chunk(perm_algo algo, int m, int n, perm_dtype dt, const void *dA,
   if (chunk >= (1ull << (nbits - chunk_log2))) return PERM_E_INVALID;
   return run_gray(algo == PERM_ALGO_GLYNN ? 0 : 1, M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind,
                   chunk_log2, chunk);
+}
+
+int perm_column_sweep(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
+                      void *dOut, uint32_t flags, void *stream) {
+  int kind = 0;
+  int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int tr = m > n;
+  const int M = std::min(m, n), N = std::max(m, n);
+  if (M == 0) return launch_write_one(ot, dOut, s) == hipSuccess ? PERM_OK : PERM_E_HIP;
+  if (N > kMaxN) return PERM_E_TOO_LARGE;
+  return run_sweep(M, N, dt, dA, lda, tr, ot, dOut, flags, s, kind);
 }
 
 int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,

@@ -276,6 +276,15 @@ hipError_t launch_batched_small_cplx(int n, const BatchBucket &bk, const BatchLa
                                      hipStream_t s);
 int batched_blocks_per_cu(int kind, int n);  // resident 256-thread workgroups per CU
 
+// The column sweep (sweep.hip) on the logical m x n matrix (m <= n): two
+// zeroed state buffers of state_bytes << m bytes each, the first ncols
+// columns (n for the whole sum; fewer only to time part of it), the value at
+// the full row set written to dOut.
+#define SWEEP_MAX_M 28
+hipError_t launch_sweep(int kind, int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                        void *buf0, void *buf1, size_t state_bytes, perm_out ot, void *dOut,
+                        hipStream_t s, int ncols);
+
 // Writes the value 1 in the output type (the permanent of an empty matrix).
 hipError_t launch_write_one(perm_out ot, void *dOut, hipStream_t s);
 
