@@ -227,6 +227,7 @@ def suite(args):
         chunks(args)
     if not args.no_batched:
         batched(args)
+        batched_01(args)
     if not args.no_selector:
         selector_stream(args)
 
@@ -327,6 +328,21 @@ def batched(args, count: int = 200_000, sample: int = 20_000, emit: bool = True)
     vs = single.view(-1, 2)
     maxdiff = float((vb - vs).abs().max())
     bound = float(torch.sqrt((out.view(-1, 2) ** 2).sum(1)).max())
+    # against the oracle's stored double-double values of the first matrices
+    err = None
+    gold = os.path.join(ROOT, "tests", "golden", "batch_reference.json")
+    if os.path.exists(gold):
+        ref = json.load(open(gold)).get("boson_200000_c128_n4..20")
+        if ref:
+            rv = np.array(ref["values"])
+            want = (rv[:, 0] + rv[:, 1]) + 1j * (rv[:, 2] + rv[:, 3])
+            got = out[:2 * len(want)].view(-1, 2).cpu().numpy()
+            got = got[:, 0] + 1j * got[:, 1]
+            d = np.abs(got - want)
+            err = {"matrices": int(len(want)), "max_abs_err": float(d.max()),
+                   "max_rel_err": float(np.max(d / np.abs(want))),
+                   "note": "|per| <= 1 for submatrices of a unitary; the 1e-11 per(|A|) "
+                           "criterion is checked by the GPU tests"}
     rec = {"workload": "batched_boson_200000_c128_n4..20", "count": count,
            "terms": terms, "graph_ms": t_batch * 1e3, "packing_autotuned": tuned_pack,
            "graph_ms_rule_packing": t_rule * 1e3, "packing_rule": rule_pack,
@@ -334,10 +350,69 @@ def batched(args, count: int = 200_000, sample: int = 20_000, emit: bool = True)
            "single_launch_perms_per_s": 1.0 / t_single, "single_launch_sample": sample,
            "speedup_vs_single_launches": t_single * count / t_batch,
            "max_abs_diff_vs_single_on_sample": maxdiff,
-           "max_abs_per": bound}
+           "max_abs_per": bound, "error_vs_oracle": err}
     if emit:
         print(json.dumps(rec), flush=True)
     plan.close()
+    return rec
+
+
+def batched_01(args, count: int = 20_000, sample: int = 2_000, emit: bool = True):
+    """20,000 square 0/1 matrices (orders 8..24, density 1/2: perfect
+    matchings of random bipartite graphs), exact int128: one perm_auto batch
+    plan (Ryser per matrix) replayed as a graph, against one perm_ryser call
+    per matrix on the first `sample`; bit-exact against the oracle's values of
+    the first matrices."""
+    import numpy as np
+    import torch
+
+    import paper_2510_03421_amd as pg
+    import workloads
+    from paper_2510_03421_amd import _capi as C
+    b = workloads.bernoulli_batch(count, 8, 24, 0.5, seed=6500)
+    data = torch.from_numpy(b.data).cuda()
+    plan = pg.BatchPlan(b.m, b.n, b.offset, b.ld, torch.uint8, algo="auto")
+    out = plan.new_output()
+    plan.run(data, out)
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run(data, out)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    single = torch.empty(2 * sample, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    dptr = data.data_ptr()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(sample):
+        n = int(b.n[i])
+        C.check(C.lib.perm_ryser(n, n, C.PERM_B8, dptr + int(b.offset[i]), n, C.PERM_OUT_I128,
+                                 single.data_ptr() + 16 * i, C.PERM_FLAG_WRAP, stream),
+                "perm_ryser")
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / sample
+    words = out.cpu().numpy().view(np.uint64).reshape(-1, 2)
+    vals = [(int(hi) << 64) | int(lo) for lo, hi in words]
+    same = bool(torch.equal(out[:2 * sample], single))
+    exact = None
+    gold = os.path.join(ROOT, "tests", "golden", "batch_reference.json")
+    if os.path.exists(gold):
+        ref = json.load(open(gold)).get("bernoulli_20000_b8_n8..24")
+        if ref:
+            want = [int(v) for v in ref["values"]]
+            exact = {"matrices": len(want), "all_equal": vals[:len(want)] == want}
+    terms = float(np.sum(2.0 ** b.n.astype(np.float64)))
+    rec = {"workload": "batched_bernoulli_20000_b8_n8..24_p0.5", "count": count,
+           "output": "int128", "algorithm": "auto (Ryser per matrix)", "terms": terms,
+           "graph_ms": t_batch * 1e3, "perms_per_s": count / t_batch,
+           "terms_per_s": terms / t_batch, "single_launch_perms_per_s": 1.0 / t_single,
+           "single_launch_sample": sample, "speedup_vs_single_launches": t_single * count / t_batch,
+           "equal_to_single_calls_on_sample": same, "exact_vs_oracle": exact}
+    plan.close()
+    if emit:
+        print(json.dumps(rec), flush=True)
     return rec
 
 
@@ -350,7 +425,9 @@ def selector_stream(args, cap_ms: float = 100.0, emit: bool = True):
     algorithms of the network and of the table alone, always Glynn (Ryser
     where Glynn's limits refuse), always Ryser (Glynn where Ryser's refuse).  Permanents per second over the stream, one warm pass per
     policy first.  Also the totals the stored timings give over all held-out
-    cases (where a wrong choice can cost minutes)."""
+    cases (where a wrong choice can cost minutes).  The candidates are the
+    paper's three algorithms, the e_m form (rectangular) and the column
+    sweep."""
     import numpy as np
     import torch
 
@@ -381,7 +458,8 @@ def selector_stream(args, cap_ms: float = 100.0, emit: bool = True):
         return run
 
     auto = lambda a, flags, density: pg.auto(a, flags=flags, density=density)
-    fns = {"combinatoric": pg.combinatoric, "ryser": pg.ryser, "glynn": pg.glynn}
+    fns = {"combinatoric": pg.combinatoric, "ryser": pg.ryser, "glynn": pg.glynn,
+           "glynn_esym": pg.glynn_esym, "column_sweep": pg.column_sweep}
 
     def first_choice(weights):
         # the selector's first choice among the three algorithms (no e_m form),
@@ -560,6 +638,7 @@ def main():
         # the metric's second part: batched permanents per second (one graph
         # launch) against one perm_glynn call per matrix on a sample
         line["batched"] = batched(args, sample=2_000, emit=False)
+        line["batched_01"] = batched_01(args, emit=False)
     line["env"] = environment()
     if not args.no_selector:
         # single permanents of mixed shapes: perm_auto against fixed algorithms

@@ -44,7 +44,7 @@
  *   PERM_E_OVERFLOW    an integer output could exceed its type (pre-check bound
  *                      prod_i sum_j |a_ij| >= 2^63 or 2^127) and PERM_FLAG_WRAP
  *                      was not given, or an exact integer product could not be
- *                      formed (an absolute row or column sum >= 2^53)
+ *                      formed (an absolute row or column sum >= 2^52)
  *   PERM_E_HIP         a HIP runtime call failed
  *   PERM_E_UNSUPPORTED the combination of arguments is not implemented
  */
@@ -96,7 +96,7 @@ typedef enum perm_algo {
   PERM_ALGO_COMBINATORIC = 0,
   PERM_ALGO_RYSER = 1,
   PERM_ALGO_GLYNN = 2,
-  PERM_ALGO_GLYNN_ESYM = 3, /* perm_glynn_esym; reported by perm_auto only */
+  PERM_ALGO_GLYNN_ESYM = 3, /* perm_glynn_esym */
   PERM_ALGO_AUTO = 4,       /* batch plans: the sum chosen per matrix */
   PERM_ALGO_SWEEP = 5       /* perm_column_sweep */
 } perm_algo;
@@ -202,9 +202,36 @@ int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, pe
  * subsets of size m-k with weight (-1)^k C(n-m+k, k)).  Square: Gray-code
  * order over the 2^n column subsets; rectangular: the subsets of each size
  * s <= m in revolving-door order.  Limits: square n <= 48 (floating point)
- * or n <= 40 (integer); rectangular min(m, n) <= 40 and max(m, n) <= 64. */
+ * or n <= 40 (integer); rectangular min(m, n) <= 40 and max(m, n) <= 64.
+ * Square with an integer output: a row whose nonzeros all lie in a column
+ * set U has an empty sum, so a zero term, for every subset that misses
+ * them; when sparse rows make this worthwhile (perm_ryser_window_plan), the
+ * columns of U go on the top Gray bits and only their states that meet
+ * every such row are walked.  The result is the same integer.  The
+ * environment variable PERM_RYSER_WINDOW=0 keeps the whole walk; =2 takes
+ * a window whenever one prunes any state. */
 int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                void *dOut, uint32_t flags, void *stream);
+
+/* perm_ryser_window_plan -- the column window perm_ryser uses for a square
+ * n x n integer matrix (host only, no device call).  row_masks: HOST
+ * uint64[n], bit j of row i set iff a_ij != 0.  lanes_max: the walk's lane
+ * count (a power of two >= 256; the device's is resident workgroups x 256).
+ * The window U is grown from the rows with the fewest nonzeros while it
+ * holds at most min(16, n - 10) columns, and kept only if the model time
+ * of the pruned walk (blocks per lane x block cost) is below 0.8 of the
+ * whole walk's (force != 0: whenever it prunes a state).  Returns 1 and fills *fw = |U|, *b = log2 of the block
+ * length, *wlow = block-index bits under the window state, *nstates = the
+ * number of states of U that meet every row inside U, col_order (may be
+ * NULL; HOST int32[n]: Gray bit q toggles column col_order[q], the window
+ * on bits n - fw .. n - 1 in ascending column order) and states (may be
+ * NULL; HOST uint32[states_cap]: bit p set = column col_order[n - fw + p]
+ * in the subset; PERM_E_TOO_LARGE if more than states_cap); returns 0 (and
+ * zeros) when the whole walk is kept; PERM_E_INVALID for n outside 0..64
+ * or a null pointer. */
+int perm_ryser_window_plan(int n, const uint64_t *row_masks, uint64_t lanes_max, int force,
+                           int *fw, int *b, int *wlow, uint64_t *nstates, int32_t *col_order,
+                           uint32_t *states, uint64_t states_cap);
 
 /* perm_gray_chunk -- one chunk of the Gray-code sum of perm_glynn (algo
  * PERM_ALGO_GLYNN, square or rectangular) or of square perm_ryser (algo
@@ -246,19 +273,21 @@ int perm_column_sweep(int m, int n, perm_dtype dt, const void *dA, int64_t lda, 
 int perm_combinatoric(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                       void *dOut, uint32_t flags, void *stream);
 
-/* perm_auto -- ranks the algorithms whose size limits admit the shape by
+/* perm_auto -- ranks the algorithms whose size limits admit the shape
+ * (combinatoric, Ryser, Glynn, the e_m form for m <= n, the column sweep) by
  * (m, n, density, dtype) with the learned selector if one is loaded
- * (perm_selector_load), else with the threshold table modelled on the
- * paper's Alg. 5 (App. B), and runs the first one; if that one refuses the
- * input with PERM_E_TOO_LARGE or PERM_E_OVERFLOW (e.g. Glynn's integer sum
- * carries an extra factor 2^(n-1) (n-m)!) the next one is tried.  For m < n,
- * perm_glynn_esym runs instead (if it accepts the input) when its
- * operation count, 2^(m-1) n (min(m, 32) + 1), is below half that of the
- * first choice (terms times 2n for Glynn, 2m for Ryser, m for the definition).  The value
- * does not depend on the choice beyond rounding; integer outputs are
- * identical.  *chosen (may be NULL) receives the algorithm that ran.
- * density < 0 means "unknown" (treated as 1).  Returns the last refusal if
- * every algorithm refuses. */
+ * (perm_selector_load: the network predicts each one's run time), else with
+ * the threshold table modelled on the paper's Alg. 5 (App. B) -- its choice
+ * among the paper's three algorithms first, or the e_m form when its
+ * operation count, 2^(m-1) n (min(m, 32) + 1), is below half of that choice's
+ * (terms times 2n for Glynn, 2m for Ryser, m for the definition), the column
+ * sweep last -- and runs the first one; if that one refuses the input with
+ * PERM_E_TOO_LARGE or PERM_E_OVERFLOW (e.g. Glynn's integer sum carries an
+ * extra factor 2^(n-1) (n-m)!) the next one is tried.  The value does not
+ * depend on the choice beyond rounding; integer outputs are identical.
+ * *chosen (may be NULL) receives the algorithm that ran.  density < 0 means
+ * "unknown" (treated as 1).  Returns the last refusal if every algorithm
+ * refuses. */
 int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
               void *dOut, uint32_t flags, void *stream, double density, perm_algo *chosen);
 
@@ -381,9 +410,9 @@ int perm_auto_batched(int count, const int32_t *hM, const int32_t *hN, const int
  * weights stay loaded). */
 int perm_selector_load(const char *path);
 
-/* The selector's first choice among the three algorithms of Sec. 1.2 (the
- * e_m override of perm_auto is not applied), without running anything, for
- * the default output type of dt (PERM_I64 / PERM_B8: exact integers).
+/* The selector's first choice (the algorithm perm_auto would try first),
+ * without running anything, for the default output type of dt (PERM_I64 /
+ * PERM_B8: exact integers).
  * *source (may be NULL) receives 1 if the network decided, 0 for the table.
  * PERM_E_TOO_LARGE if no algorithm admits the shape. */
 int perm_select(int m, int n, perm_dtype dt, double density, perm_algo *chosen, int *source);
@@ -401,11 +430,13 @@ int perm_selector_features(int m, int n, perm_dtype dt, double density, float *x
  * fraction < 1 the algorithm's main kernel does only about that fraction of
  * the work of each lane or wave, so that a caller can extrapolate the time of
  * a long run from short ones (the time is about a + b x for the fraction x
- * run): Glynn and square Ryser run fewer Gray-code blocks per lane (never
- * fewer than two), in rectangular Ryser every wave stops after that fraction
- * of its share of the work (its last item's walks cut short), the
- * combinatoric sum runs whole rounds of its map prefixes (at least one), so
- * its x can differ from `fraction` by a round.  *fraction_run (may be NULL)
+ * run): Glynn, square Ryser and the e_m form run fewer Gray-code blocks per
+ * lane (never fewer than two), in rectangular Ryser every wave stops after
+ * that fraction of its share of the work (its last item's walks cut short),
+ * the combinatoric sum runs whole rounds of its map prefixes (at least one),
+ * so its x can differ from `fraction` by a round, and the column sweep runs
+ * its first columns up to about that share of its state updates.  algo is
+ * any perm_algo but PERM_ALGO_AUTO.  *fraction_run (may be NULL)
  * receives the fraction x actually run.  The value computed
  * is discarded.  Errors: those of the algorithm's entry point, and
  * PERM_E_INVALID for fraction outside (0, 1], reps < 1 or ms NULL.
@@ -415,16 +446,18 @@ int perm_time(perm_algo algo, int m, int n, perm_dtype dt, const void *dA, int64
               double *fraction_run);
 
 /* ---- the selector network on the GPU (FP32) ----
- * Network 4 -> 64 -> 64 -> 3 with ReLU hidden layers on normalised features
- * z = (x - mean) / std, outputs y[k] = predicted log run time of perm_algo k.
+ * Network 4 -> 64 -> 64 -> 5 with ReLU hidden layers on normalised features
+ * z = (x - mean) / std, outputs y[k] = predicted log run time (ms) of
+ * algorithm k in the order combinatoric, Ryser, Glynn, the e_m form
+ * (perm_glynn_esym), the column sweep (perm_column_sweep).
  * Parameters: one DEVICE array of PERM_MLP_PARAMS floats,
- *   W1[64][4] | b1[64] | W2[64][64] | b2[64] | W3[3][64] | b3[3]
+ *   W1[64][4] | b1[64] | W2[64][64] | b2[64] | W3[5][64] | b3[5]
  * (weights row-major [output][input]); norm: DEVICE float[8] = mean[4] | std[4].
- * X: DEVICE float[batch][4]; T, Y: DEVICE float[batch][3].  A NaN target
+ * X: DEVICE float[batch][4]; T, Y: DEVICE float[batch][5].  A NaN target
  * (algorithm not available for that shape) takes no part in the loss
  *   L = scale * sum over finite T[b][k] of (Y[b][k] - T[b][k])^2.
  * All three are asynchronous on `stream` and deterministic (fixed-order sums). */
-#define PERM_MLP_PARAMS 4675
+#define PERM_MLP_PARAMS 4805
 
 /* Y = network(X). */
 int perm_mlp_forward(const float *dParams, const float *dNorm, const float *dX, int batch,
@@ -454,7 +487,7 @@ int perm_mlp_adam(float *dParams, const float *dGrad, float *dState, float lr, f
  * replayed `epochs` times.  On return hParams holds the trained parameters and
  * hLoss (HOST float[epochs], may be NULL) the loss before each step.  hX:
  * HOST float[count][4] features (perm_selector_features), hT: HOST
- * float[count][3] log run times.  Synchronous. */
+ * float[count][5] log run times.  Synchronous. */
 int perm_selector_train(int count, const float *hX, const float *hT, int epochs, float lr,
                         uint64_t seed, int init, float *hParams, float *hNorm, float *hLoss,
                         void *stream);

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY: used by tests/ to check the GPU kernels' forward
 pass, gradient and Adam step.  Nothing in the library imports it.
 
-The network is a plain multilayer perceptron 4 -> 64 -> 64 -> 3 with ReLU
+The network is a plain multilayer perceptron 4 -> 64 -> 64 -> 5 with ReLU
 hidden layers on normalised inputs z = (x - mean) / std; its loss is the
 squared error over the finite targets, L = scale * sum (y - t)^2.  The
 gradient is written out by the chain rule, layer by layer (backpropagation),
@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-IN, H, OUT = 4, 64, 3
+IN, H, OUT = 4, 64, 5
 LAYOUT = (("W1", (H, IN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (OUT, H)),
           ("b3", (OUT,)))
 NPARAMS = sum(int(np.prod(s)) for _, s in LAYOUT)
@@ -37,7 +37,7 @@ def pack(w: dict) -> np.ndarray:
 
 
 def forward(p, norm, x):
-    """Outputs y[B][3] and the activations the gradient needs."""
+    """Outputs y[B][OUT] and the activations the gradient needs."""
     w = unpack(p)
     norm = np.asarray(norm, dtype=np.float64)
     z = (np.asarray(x, dtype=np.float64) - norm[:IN]) / norm[IN:]

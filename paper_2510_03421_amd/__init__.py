@@ -185,6 +185,32 @@ def select(m: int, n: int, dtype: torch.dtype = torch.float64, density: float = 
     return ALGORITHMS[chosen.value], bool(src.value)
 
 
+def ryser_window_plan(row_masks, lanes_max: int, force: bool = False):
+    """The column window square integer ``ryser`` walks for an n x n matrix
+    with nonzero pattern ``row_masks`` (n ints, bit j of row i = a_ij != 0):
+    None for the whole walk, else a dict with fw, b, wlow, col_order and
+    states (host only).  ``force``: any window that prunes (what
+    PERM_RYSER_WINDOW=2 makes perm_ryser use)."""
+    import numpy as np
+    rm = np.ascontiguousarray(np.asarray(row_masks, dtype=np.uint64))
+    n = rm.size
+    fw, b, wlow = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    ns = ctypes.c_uint64(0)
+    col = np.zeros(max(n, 1), dtype=np.int32)
+    cap = 1 << 16
+    st = np.zeros(cap, dtype=np.uint32)
+    rc = C.lib.perm_ryser_window_plan(n, rm.ctypes.data, int(lanes_max), int(force),
+                                      ctypes.byref(fw),
+                                      ctypes.byref(b), ctypes.byref(wlow), ctypes.byref(ns),
+                                      col.ctypes.data, st.ctypes.data, cap)
+    if rc < 0:
+        C.check(rc, "perm_ryser_window_plan")
+    if rc == 0:
+        return None
+    return {"fw": fw.value, "b": b.value, "wlow": wlow.value, "col_order": col[:n].copy(),
+            "states": st[:ns.value].copy()}
+
+
 def selector_load(path: str | None) -> None:
     C.check(C.lib.perm_selector_load(path.encode() if path else None), "perm_selector_load")
 

@@ -74,6 +74,10 @@ lib.perm_select.argtypes = [_i32, _i32, _i32, _d, ctypes.POINTER(_i32), ctypes.P
 lib.perm_select.restype = _i32
 lib.perm_selector_features.argtypes = [_i32, _i32, _i32, _d, _p]
 lib.perm_selector_features.restype = _i32
+lib.perm_ryser_window_plan.argtypes = [_i32, _p, ctypes.c_uint64, _i32, ctypes.POINTER(_i32),
+                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                       ctypes.POINTER(ctypes.c_uint64), _p, _p, ctypes.c_uint64]
+lib.perm_ryser_window_plan.restype = _i32
 lib.perm_time.argtypes = [_i32, _i32, _i32, _i32, _p, _i64, _i32, _u32, _d, _i32, _p,
                           ctypes.POINTER(_d), ctypes.POINTER(_d)]
 lib.perm_time.restype = _i32
@@ -89,7 +93,7 @@ lib.perm_selector_train.argtypes = [_i32, _p, _p, _i32, _f, ctypes.c_uint64, _i3
 lib.perm_selector_train.restype = _i32
 lib.perm_selector_save.argtypes = [ctypes.c_char_p, _p, _p, _p]
 lib.perm_selector_save.restype = _i32
-PERM_MLP_PARAMS = 4675
+PERM_MLP_PARAMS = 4805
 
 
 class PermError(RuntimeError):

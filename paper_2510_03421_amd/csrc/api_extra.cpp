@@ -106,7 +106,7 @@ int perm_select(int m, int n, perm_dtype dt, double density, perm_algo *chosen, 
   const int M = std::min(m, n), N = std::max(m, n);
   // the engine kind of the default output type of dt (integers: exact)
   const int kind = dt == PERM_C128 ? ENGINE_CPLX : dt == PERM_F64 ? ENGINE_REAL : ENGINE_INT;
-  perm_algo order[3];
+  perm_algo order[kSelOut];
   int src = 0;
   const int cnt = rank_algorithms(M, N, dt, density, algo_mask(M, N, kind), order, &src);
   if (cnt == 0) return PERM_E_TOO_LARGE;
@@ -115,40 +115,33 @@ int perm_select(int m, int n, perm_dtype dt, double density, perm_algo *chosen, 
   return PERM_OK;
 }
 
+static int run_one(perm_algo a, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
+                   perm_out ot, void *dOut, uint32_t flags, void *stream) {
+  switch (a) {
+    case PERM_ALGO_COMBINATORIC: return perm_combinatoric(m, n, dt, dA, lda, ot, dOut, flags, stream);
+    case PERM_ALGO_RYSER: return perm_ryser(m, n, dt, dA, lda, ot, dOut, flags, stream);
+    case PERM_ALGO_GLYNN_ESYM: return perm_glynn_esym(m, n, dt, dA, lda, ot, dOut, flags, stream);
+    case PERM_ALGO_SWEEP: return perm_column_sweep(m, n, dt, dA, lda, ot, dOut, flags, stream);
+    default: return perm_glynn(m, n, dt, dA, lda, ot, dOut, flags, stream);
+  }
+}
+
 int perm_auto(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot, void *dOut,
               uint32_t flags, void *stream, double density, perm_algo *chosen) {
   int kind = 0;
   int rc = validate(m, n, dt, dA, lda, ot, dOut, kind);
   if (rc) return rc;
   const int M = std::min(m, n), N = std::max(m, n);
-  perm_algo order[3];
+  perm_algo order[kSelOut];
   int src = 0;
   const int cnt = rank_algorithms(M, N, dt, density, algo_mask(M, N, kind), order, &src);
   if (cnt == 0) return PERM_E_TOO_LARGE;
-  // the e_m form for rectangular floating-point problems when it needs well
-  // under the operations of the selector's first choice
-  if (M > 0 && M < N && M <= ESYM_MAX_M && N <= 48) {
-    const double lg_esym = (double)(M - 1) + std::log2((double)N * (std::min(M, ESYM_MAX_M) + 1));
-    const perm_algo a = order[0];
-    const double per_term = a == PERM_ALGO_GLYNN ? 2.0 * N : (a == PERM_ALGO_RYSER ? 2.0 * M : M);
-    if (lg_esym + 1.0 < log2_algo_terms(a, M, N) + std::log2(per_term)) {
-      rc = perm_glynn_esym(m, n, dt, dA, lda, ot, dOut, flags, stream);
-      if (rc == PERM_OK && chosen) *chosen = PERM_ALGO_GLYNN_ESYM;
-      if (rc != PERM_E_TOO_LARGE && rc != PERM_E_OVERFLOW) return rc;
-    }
-  }
-  // in predicted order; an algorithm that refuses the input (size limit, or
-  // an integer bound that only it cannot meet, such as Glynn's extra factor
+  // in ranked order; an algorithm that refuses the input (size limit, or an
+  // integer bound that only it cannot meet, such as Glynn's extra factor
   // 2^(n-1) (n-m)!) passes to the next one
   rc = PERM_E_TOO_LARGE;
   for (int i = 0; i < cnt; ++i) {
-    switch (order[i]) {
-      case PERM_ALGO_COMBINATORIC:
-        rc = perm_combinatoric(m, n, dt, dA, lda, ot, dOut, flags, stream);
-        break;
-      case PERM_ALGO_RYSER: rc = perm_ryser(m, n, dt, dA, lda, ot, dOut, flags, stream); break;
-      default: rc = perm_glynn(m, n, dt, dA, lda, ot, dOut, flags, stream); break;
-    }
+    rc = run_one(order[i], m, n, dt, dA, lda, ot, dOut, flags, stream);
     if (rc != PERM_E_TOO_LARGE && rc != PERM_E_OVERFLOW) {
       if (rc == PERM_OK && chosen) *chosen = order[i];
       return rc;

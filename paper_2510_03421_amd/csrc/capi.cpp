@@ -379,6 +379,152 @@ int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out 
 }
 
 // ------------------------------------------------------------------ //
+// square Ryser: pruning by a window of columns                       //
+// ------------------------------------------------------------------ //
+// Row i's sum over a column subset S is empty -- the term is zero -- when S
+// misses every nonzero column of row i.  Put the columns U that hold all
+// the nonzeros of some sparse rows on the top Gray bits, constant over the
+// blocks of a wave: of the 2^|U| states of those bits, only the ones that
+// meet every such row can give a nonzero term, and the walk visits only
+// those.  Exact for any values: the skipped terms have an empty row sum.
+struct RyserWindow {
+  std::vector<int32_t> col_order;  // Gray bit q toggles column col_order[q]
+  std::vector<uint32_t> states;    // bit p = column col_order[n - fw + p]
+  int fw = 0;                      // window width
+  int wlow = 0;                    // block index bits below the window state
+  uint64_t wblocks = 0;            // states << wlow
+  GrayPlan plan;
+};
+
+static int read_row_masks(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                          std::vector<uint64_t> &out, hipStream_t s) {
+  out.assign(M, 0);
+  uint64_t *d = nullptr;
+  if (hipMallocAsync((void **)&d, sizeof(uint64_t) * (size_t)std::max(M, 1), s) != hipSuccess)
+    return PERM_E_HIP;
+  hipError_t e = launch_row_masks(M, N, dt, dA, lda, tr, d, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out.data(), d, sizeof(uint64_t) * (size_t)M, hipMemcpyDeviceToHost, s);
+  hipError_t e2 = hipFreeAsync(d, s);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+}
+
+// Relative time of an engine walk: blocks per lane times one block (2^b
+// steps of an update and a product over nv entries, plus the closed-form
+// seed of nbits - b + 1 table rows).
+static double engine_walk_cost(uint64_t bpl, int nv, int nbits, int b) {
+  return (double)bpl * (std::ldexp(2.0 * nv + 20.0, b) + (double)(nbits - b + 1) * nv);
+}
+
+// The window: the sparsest rows, taken while their columns fit, with the
+// block length that keeps every lane busy; false if it does not save at
+// least a fifth of the whole walk's time.
+static bool plan_ryser_window(const std::vector<uint64_t> &masks, int n, uint64_t lanes_max,
+                              bool force, RyserWindow &out) {
+  const int m = (int)masks.size();
+  // wave-uniform window states need 7 block-index bits below them (64
+  // lanes, two block parities), and blocks are at least 8 steps
+  const int fw_cap = std::min(16, n - 7 - 3);
+  if (fw_cap < 0 || lanes_max < 256 || n > 64 || m != n) return false;
+  // the whole walk's plan (as plan_gray_bpc makes it)
+  const int b0 = std::min(n, std::max(3, std::min(n - ilog2(lanes_max) - 1, 12)));
+  const uint64_t nblk = 1ull << (n - b0);
+  const uint64_t bpl0 = nblk == 1 ? 1 : nblk / std::min<uint64_t>(lanes_max, nblk / 2);
+  std::vector<int> rows(m);
+  for (int i = 0; i < m; ++i) rows[i] = i;
+  std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) {
+    return __builtin_popcountll(masks[x]) < __builtin_popcountll(masks[y]);
+  });
+  const double dense_cost = engine_walk_cost(bpl0, n, n, b0);
+  // force: any window that prunes, at its best block length
+  double best = force ? HUGE_VAL : 0.8 * dense_cost;
+  bool found = false;
+  uint64_t U = 0;
+  std::vector<uint64_t> st{0};  // surviving states, as column masks within U
+  for (int i : rows) {
+    const uint64_t mr = masks[i];
+    const uint64_t nu = U | mr;
+    if (__builtin_popcountll(nu) > fw_cap) continue;
+    // extend every state by each subset x of the new columns, keep those
+    // that meet row i
+    const uint64_t nb = mr & ~U;
+    std::vector<uint64_t> nx;
+    for (uint64_t t : st) {
+      uint64_t x = 0;
+      do {
+        if ((t | x) & mr) nx.push_back(t | x);
+        x = (x - nb) & nb;
+      } while (x != 0);
+    }
+    if (nx.size() > (1u << 16)) break;
+    U = nu;
+    st.swap(nx);
+    const int fw = __builtin_popcountll(U);
+    for (int b = 3; b <= 12; ++b) {
+      const int L = n - fw - b;
+      if (L < 7) break;
+      const uint64_t T = (uint64_t)st.size() << L;
+      const uint64_t lanes = std::min<uint64_t>(lanes_max, std::max<uint64_t>(256, ((T / 2 + 255) / 256) * 256));
+      const uint64_t bpl = 2 * ((T + 2 * lanes - 1) / (2 * lanes));
+      const double cost = T == 0 ? 0.0 : engine_walk_cost(bpl, n, n, b);
+      if (cost < best && st.size() < (1ull << fw)) {
+        best = cost;
+        found = true;
+        out.fw = fw;
+        out.wlow = L;
+        out.wblocks = T;
+        out.plan.b = b;
+        out.plan.lanes = lanes;
+        out.plan.blocks_per_lane = std::max<uint64_t>(2, bpl);
+        out.plan.block = (int)std::min<uint64_t>(256, lanes);
+        out.plan.grid = (int)(lanes / (uint64_t)out.plan.block);
+        // window columns in ascending order on Gray bits n - fw .. n - 1
+        std::vector<int> ucols;
+        for (int j = 0; j < n; ++j)
+          if ((U >> j) & 1u) ucols.push_back(j);
+        out.col_order.clear();
+        for (int j = 0; j < n; ++j)
+          if (!((U >> j) & 1u)) out.col_order.push_back(j);
+        for (int j : ucols) out.col_order.push_back(j);
+        out.states.resize(st.size());
+        for (size_t k = 0; k < st.size(); ++k) {
+          uint32_t v = 0;
+          for (int p = 0; p < fw; ++p)
+            if ((st[k] >> ucols[p]) & 1u) v |= 1u << p;
+          out.states[k] = v;
+        }
+      }
+    }
+    if (st.empty()) break;  // a row with no nonzero: nothing is left to walk
+  }
+  return found;
+}
+
+extern "C" int perm_ryser_window_plan(int n, const uint64_t *row_masks, uint64_t lanes_max,
+                                      int force, int *fw, int *b, int *wlow, uint64_t *nstates,
+                                      int32_t *col_order, uint32_t *states,
+                                      uint64_t states_cap) {
+  if (n < 0 || n > 64 || (n > 0 && !row_masks) || !fw || !b || !wlow || !nstates)
+    return PERM_E_INVALID;
+  RyserWindow win;
+  const bool use = plan_ryser_window(std::vector<uint64_t>(row_masks, row_masks + n), n,
+                                     lanes_max, force != 0, win);
+  *fw = use ? win.fw : 0;
+  *b = use ? win.plan.b : 0;
+  *wlow = use ? win.wlow : 0;
+  *nstates = use ? win.states.size() : 0;
+  if (!use) return 0;
+  if (col_order) std::copy(win.col_order.begin(), win.col_order.end(), col_order);
+  if (states) {
+    if (win.states.size() > states_cap) return PERM_E_TOO_LARGE;
+    std::copy(win.states.begin(), win.states.end(), states);
+  }
+  return 1;
+}
+
+// ------------------------------------------------------------------ //
 // the Gray-walk path (Glynn square/rectangular, Ryser square)        //
 // ------------------------------------------------------------------ //
 int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
@@ -403,6 +549,22 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
   GrayPlan plan;
   int rc = plan_gray(kind, nv, nbits, plan);
   if (rc) return rc;
+  // exact square Ryser over the whole walk: prune the column subsets that
+  // leave a sparse row empty (the host already waits for the pre-check here)
+  RyserWindow win;
+  bool use_win = false;
+  // PERM_RYSER_WINDOW: 0 = always the whole walk, 2 = a window whenever one
+  // prunes (for tests at orders where the model keeps the whole walk)
+  const int win_mode = env_int("PERM_RYSER_WINDOW", 1);
+  if (kind == ENGINE_INT && algo == 1 && chunk_log2 < 0 && nbits >= 3 && win_mode != 0) {
+    std::vector<uint64_t> masks;
+    rc = read_row_masks(M, N, dt, dA, lda, tr, masks, s);
+    if (rc) return rc;
+    const uint64_t lanes_max =
+        pow2_floor((uint64_t)device_cus() * (uint64_t)gray_engine_blocks_per_cu_int(nv) * 256u);
+    use_win = plan_ryser_window(masks, N, lanes_max, win_mode == 2, win);
+    if (use_win) plan = win.plan;
+  }
   uint64_t bpl_run = plan.blocks_per_lane;
   const double f = tune_fraction();
   if (f < 1.0 && plan.blocks_per_lane >= 4) {
@@ -415,7 +577,8 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
   const size_t tbl_n = (size_t)2 * nbits_all * nv * C;
   const size_t base_n = (size_t)nv * C;
   const size_t part_n = (size_t)plan.grid * 2 * C;
-  const size_t bytes = sizeof(double) * (tbl_n + base_n + part_n) + 256;
+  const size_t win_n = use_win ? win.col_order.size() + win.states.size() : 0;
+  const size_t bytes = sizeof(double) * (tbl_n + base_n + part_n) + 256 + sizeof(int32_t) * win_n;
   char *scratch = nullptr;
   if (ext_scratch) {
     if (bytes > ext_bytes) return PERM_E_TOO_LARGE;
@@ -434,8 +597,23 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     pad_exp = (int *)(part + part_n);
     e = launch_pad_scale(M, N, dt, dA, lda, tr, pad_exp, s);
   }
+  int32_t *dcol = nullptr;
+  uint32_t *dstates = nullptr;
+  if (use_win && e == hipSuccess) {
+    // column order and states: one copy, waited for before the host
+    // vectors go out of scope
+    std::vector<int32_t> host(win_n);
+    std::copy(win.col_order.begin(), win.col_order.end(), host.begin());
+    for (size_t i = 0; i < win.states.size(); ++i)
+      host[win.col_order.size() + i] = (int32_t)win.states[i];
+    dcol = (int32_t *)((char *)(part + part_n) + 256);
+    dstates = (uint32_t *)(dcol + win.col_order.size());
+    e = hipMemcpyAsync(dcol, host.data(), sizeof(int32_t) * win_n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
   if (e == hipSuccess)
-    e = launch_stage_gray(algo, M, N, dt, dA, lda, tr, tbl, base, C == 2, s, pad_exp, g_start);
+    e = launch_stage_gray(algo, M, N, dt, dA, lda, tr, tbl, base, C == 2, s, pad_exp, g_start,
+                          dcol);
   if (e == hipSuccess) {
     GrayWalk w;
     w.tbl = tbl;
@@ -447,6 +625,13 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     // 0/1 Ryser: row sums are never negative
     w.nonneg = kind == ENGINE_INT && dt == PERM_B8 && algo == 1;
     w.blocks_per_lane = bpl_run;
+    if (use_win) {
+      // never read when no state survives (wblocks = 0), but non-null
+      w.wlist = win.states.empty() ? (const uint32_t *)dcol : dstates;
+      w.wblocks = win.wblocks;
+      w.wlow = win.wlow;
+      w.wshift = N - win.fw;
+    }
     profile_begin(s);
     if (nbits < 3) {
       e = launch_gray_tiny(kind, w, part, s);

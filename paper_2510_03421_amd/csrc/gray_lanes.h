@@ -35,6 +35,11 @@ struct Lane<NV, ENGINE_REAL> {
   double v[NV];
   double s, hi, lo;
   __device__ __forceinline__ void zero_acc() { s = hi = lo = 0.0; }
+  __device__ __forceinline__ void negate_acc() {
+    s = -s;
+    hi = -hi;
+    lo = -lo;
+  }
   __device__ __forceinline__ void load_base(const double *__restrict__ base) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = base[j];
@@ -89,6 +94,14 @@ struct Lane<NV, ENGINE_CPLX> {
   double vr[NV], vi[NV];
   double sr, si, hr, lr, hi_, li;
   __device__ __forceinline__ void zero_acc() { sr = si = hr = lr = hi_ = li = 0.0; }
+  __device__ __forceinline__ void negate_acc() {
+    sr = -sr;
+    si = -si;
+    hr = -hr;
+    lr = -lr;
+    hi_ = -hi_;
+    li = -li;
+  }
   __device__ __forceinline__ void load_base(const double *__restrict__ base) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
@@ -137,6 +150,7 @@ struct Lane<NV, ENGINE_INT> {
   int pl;       // product selector (int_chunk_count)
   bool nonneg;  // every factor >= 0 (0/1 Ryser): no sign
   __device__ __forceinline__ void zero_acc() { acc = 0; }
+  __device__ __forceinline__ void negate_acc() { acc = (u128)0 - acc; }
   __device__ __forceinline__ void load_base(const double *__restrict__ base) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = base[j];

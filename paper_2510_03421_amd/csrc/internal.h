@@ -50,6 +50,13 @@ struct GrayWalk {
   int nonneg;          // ENGINE_INT only: every factor >= 0 (no sign to track)
   uint64_t blocks_per_lane;
   int m;               // e_m walk only: the degree (number of rows)
+  // Square Ryser over a column window (engine only; null = the whole walk):
+  // the top n - wshift Gray bits take only the wcount states in wlist (the
+  // others leave some row sum empty), block blk walks state wlist[blk >>
+  // wlow] with low block bits blk mod 2^wlow; wblocks = wcount << wlow.
+  const uint32_t *wlist = nullptr;
+  uint64_t wblocks = 0;
+  int wlow = 0, wshift = 0;
 };
 
 // Rectangular Ryser by subset size (see ryser_rect.hip for the layout).
@@ -185,9 +192,15 @@ struct Finish {
 // for m<n), a square Ryser walk (algo 1) or a walk over the signs of the m
 // rows only (algo 2, for the e_m form); converts the input dtype; `tr` reads
 // A^T.
+// col_order (square Ryser only, may be null): Gray bit q toggles column
+// col_order[q] of A.
 hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
                              int tr, double *tbl, double *base, int cplx, hipStream_t s,
-                             const int *pad_exp = nullptr, uint64_t g_start = 0);
+                             const int *pad_exp = nullptr, uint64_t g_start = 0,
+                             const int32_t *col_order = nullptr);
+// out[i] = bit mask of the nonzero entries of row i (n <= 64).
+hipError_t launch_row_masks(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                            uint64_t *out, hipStream_t s);
 // The exponent of the floating-point Glynn padding value (device int *e).
 hipError_t launch_pad_scale(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
                             int *e, hipStream_t s);

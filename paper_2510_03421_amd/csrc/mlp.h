@@ -6,9 +6,9 @@
 
 namespace permgpu {
 
-constexpr int kMlpIn = 4, kMlpHidden = 64, kMlpOut = 3;
+constexpr int kMlpIn = 4, kMlpHidden = 64, kMlpOut = 5;
 constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden +
-                           kMlpHidden + kMlpOut * kMlpHidden + kMlpOut;  // 4675
+                           kMlpHidden + kMlpOut * kMlpHidden + kMlpOut;  // 4805
 
 // Number of per-workgroup partial gradients the gradient kernel writes for a
 // batch (part_grad holds mlp_groups(batch) * kMlpParams floats, part_loss

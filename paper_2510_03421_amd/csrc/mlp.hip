@@ -3,7 +3,7 @@
 //
 // Network 4 -> 64 -> 64 -> 3 with ReLU hidden layers on normalised features
 // z = (x - mean) / std.  Parameters are one flat array:
-//   W1[64][4] | b1[64] | W2[64][64] | b2[64] | W3[3][64] | b3[3]   (4675 floats)
+//   W1[64][4] | b1[64] | W2[64][64] | b2[64] | W3[5][64] | b3[5]   (4805 floats)
 // Targets t[b][k] are log run times; a NaN target (algorithm not available
 // for that shape) takes no part in the loss
 //   L = scale * sum_{b,k: t finite} (y[b][k] - t[b][k])^2.

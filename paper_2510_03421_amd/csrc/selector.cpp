@@ -86,6 +86,10 @@ unsigned algo_mask(int M, int N, int kind) {
   const int nv_max = kind == 2 ? 40 : 48;  // Gray-walk engine limits (integer / floating)
   if (M == N ? N <= nv_max : (M <= 40 && N <= 64)) mask |= 1u << PERM_ALGO_RYSER;
   if (N <= nv_max) mask |= 1u << PERM_ALGO_GLYNN;
+  // the e_m form also runs square matrices (where it is Glynn with the
+  // products taken as e_n), and is sometimes the fastest there
+  if (M <= N && M <= 32 && N <= 48) mask |= 1u << PERM_ALGO_GLYNN_ESYM;
+  if (M <= 28 && N <= 64) mask |= 1u << PERM_ALGO_SWEEP;
   return mask;
 }
 
@@ -106,13 +110,36 @@ double log2_algo_terms(perm_algo a, int M, int N) {
       }
       return std::log2(s);
     }
+    case PERM_ALGO_GLYNN_ESYM: return (double)(M - 1);
+    case PERM_ALGO_SWEEP: {
+      // states of each size k, times the columns in whose band k lies
+      double s = 0.0, c = 1.0;
+      for (int k = 0; k <= M; ++k) {
+        const int cols = std::min(N - M + 1, std::min(k + 1, N - (M - k)));
+        if (cols > 0) s += c * cols;
+        c = c * (double)(M - k) / (double)(k + 1);
+      }
+      return std::log2(std::max(s, 1.0));
+    }
     default: return (double)(N - 1);
   }
 }
 
+// log2 of a rough operation count: terms times the work of one term
+static double log2_algo_ops(perm_algo a, int M, int N) {
+  const double t = log2_algo_terms(a, M, N);
+  switch (a) {
+    case PERM_ALGO_COMBINATORIC: return t + std::log2((double)std::max(M, 1));
+    case PERM_ALGO_RYSER: return t + std::log2(2.0 * M);
+    case PERM_ALGO_GLYNN: return t + std::log2(2.0 * N);
+    case PERM_ALGO_GLYNN_ESYM: return t + std::log2((double)N * (std::min(M, 32) + 1));
+    default: return t + std::log2((double)std::max(M, 1));
+  }
+}
+
 int rank_algorithms(int M, int N, perm_dtype dt, double density, unsigned mask,
-                    perm_algo order[3], int *source) {
-  double key[3];
+                    perm_algo order[kSelOut], int *source) {
+  double key[kSelOut];
   int src = 0;
   {
     std::lock_guard<std::mutex> g(g_mu);
@@ -120,27 +147,35 @@ int rank_algorithms(int M, int N, perm_dtype dt, double density, unsigned mask,
       float x[kSelIn], y[kSelOut];
       selector_features(M, N, dt, density, x);
       mlp_forward(g_net, x, y);
-      for (int a = 0; a < 3; ++a) key[a] = y[a];  // output order = perm_algo order
+      for (int k = 0; k < kSelOut; ++k) key[k] = y[k];
       src = 1;
     } else {
       const perm_algo c = table_choice(g_net.has_table ? g_net.table : default_table(), M, N);
-      for (int a = 0; a < 3; ++a) key[a] = log2_algo_terms((perm_algo)a, M, N);
-      key[c] = -1e300;  // the table's choice first
+      for (int k = 0; k < kSelOut; ++k) key[k] = log2_algo_terms(kSelAlgo[k], M, N);
+      int first = c;  // output index = perm_algo value for the paper's three
+      // the e_m form first when it needs well under the operations of the
+      // table's choice (rectangular shapes)
+      if ((mask & (1u << PERM_ALGO_GLYNN_ESYM)) &&
+          log2_algo_ops(PERM_ALGO_GLYNN_ESYM, M, N) + 1.0 < log2_algo_ops(c, M, N))
+        first = 3;
+      key[first] = -1e300;
+      key[4] = 1e300;  // the sweep last (it trades time for accuracy)
     }
   }
-  int cnt = 0;
-  for (int a = 0; a < 3; ++a)
-    if (mask & (1u << a)) order[cnt++] = (perm_algo)a;
-  std::stable_sort(order, order + cnt, [&](perm_algo x, perm_algo y) { return key[x] < key[y]; });
+  int idx[kSelOut], cnt = 0;
+  for (int k = 0; k < kSelOut; ++k)
+    if (mask & (1u << kSelAlgo[k])) idx[cnt++] = k;
+  std::stable_sort(idx, idx + cnt, [&](int x, int y) { return key[x] < key[y]; });
+  for (int i = 0; i < cnt; ++i) order[i] = kSelAlgo[idx[i]];
   if (source) *source = src;
   return cnt;
 }
 
 // Text format (whitespace separated):
-//   permgpu-selector 1
+//   permgpu-selector 2                     (version 1 files: table only)
 //   table p1 p2 p3 p4 p5 p6 p7 p8          (optional)
 //   norm mean0..3 std0..3
-//   W1 (64x4) b1 (64) W2 (64x64) b2 (64) W3 (3x64) b3 (3)
+//   W1 (64x4) b1 (64) W2 (64x64) b2 (64) W3 (5x64) b3 (5)
 int selector_load_file(const char *path) {
   std::lock_guard<std::mutex> g(g_mu);
   if (path == nullptr) {
@@ -165,7 +200,7 @@ int selector_load_file(const char *path) {
     } else if (std::strcmp(tag, "norm") == 0) {
       for (int i = 0; i < kSelIn && ok; ++i) ok = std::fscanf(f, "%f", &net.mean[i]) == 1;
       for (int i = 0; i < kSelIn && ok; ++i) ok = std::fscanf(f, "%f", &net.stdv[i]) == 1;
-    } else if (std::strcmp(tag, "mlp") == 0) {
+    } else if (std::strcmp(tag, "mlp") == 0 && ver == 2) {  // 5 outputs since version 2
       rd(net.W1, kSelH * kSelIn);
       rd(net.b1, kSelH);
       rd(net.W2, kSelH * kSelH);

@@ -8,9 +8,12 @@
 
 namespace permgpu {
 
-// Network shape: 4 -> 64 -> 64 -> 3, ReLU hidden layers, FP32 (the same
-// network the GPU kernels train).
+// Network shape: 4 -> 64 -> 64 -> 5, ReLU hidden layers, FP32 (the same
+// network the GPU kernels train).  Output k predicts the log run time of
+// kSelAlgo[k].
 constexpr int kSelIn = kMlpIn, kSelH = kMlpHidden, kSelOut = kMlpOut;
+constexpr perm_algo kSelAlgo[kSelOut] = {PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN,
+                                         PERM_ALGO_GLYNN_ESYM, PERM_ALGO_SWEEP};
 
 // Features of a problem (the order the network sees them).
 void selector_features(int M, int N, perm_dtype dt, double density, float f[kSelIn]);
@@ -27,19 +30,23 @@ perm_algo table_choice(const ThresholdTable &t, int M, int N);
 
 // log2 of the number of terms algorithm a sums on the logical M x N shape:
 // injective maps, column subsets (square 2^N, by size sum_{s<=M} C(N, s)),
-// or Glynn's 2^(N-1) sign vectors.
+// Glynn's 2^(N-1) sign vectors, the e_m form's 2^(M-1), or the column
+// sweep's state updates.
 double log2_algo_terms(perm_algo a, int M, int N);
 
 // Algorithms whose size limits admit the logical M x N shape (M <= N) for an
-// engine kind: bit a set <=> perm_algo a can run it.
+// engine kind: bit a set <=> perm_algo a can run it (the e_m form only for
+// M < N).
 unsigned algo_mask(int M, int N, int kind);
 
 // The algorithms of `mask` in the order perm_auto tries them: by the loaded
-// network's predicted log time if a network is loaded (*source = 1), else
-// the table's choice first and the rest by their term counts (*source = 0).
-// Returns how many entries of order[] were filled.
+// network's predicted log time if a network is loaded (*source = 1); else
+// (*source = 0) the table's choice among the paper's three algorithms first
+// -- or the e_m form, for M < N, when its operation count is below half of
+// that choice's -- and the rest by their term counts.  Returns how many
+// entries of order[] were filled.
 int rank_algorithms(int M, int N, perm_dtype dt, double density, unsigned mask,
-                    perm_algo order[3], int *source);
+                    perm_algo order[kSelOut], int *source);
 
 // Load (path != NULL) or unload (NULL) network weights / table values.
 int selector_load_file(const char *path);

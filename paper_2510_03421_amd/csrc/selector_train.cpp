@@ -30,6 +30,8 @@ int run_algo(perm_algo algo, int m, int n, perm_dtype dt, const void *dA, int64_
       return perm_combinatoric(m, n, dt, dA, lda, ot, dOut, flags, stream);
     case PERM_ALGO_RYSER: return perm_ryser(m, n, dt, dA, lda, ot, dOut, flags, stream);
     case PERM_ALGO_GLYNN: return perm_glynn(m, n, dt, dA, lda, ot, dOut, flags, stream);
+    case PERM_ALGO_GLYNN_ESYM: return perm_glynn_esym(m, n, dt, dA, lda, ot, dOut, flags, stream);
+    case PERM_ALGO_SWEEP: return perm_column_sweep(m, n, dt, dA, lda, ot, dOut, flags, stream);
     default: return PERM_E_INVALID;
   }
 }
@@ -85,7 +87,8 @@ int perm_time(perm_algo algo, int m, int n, perm_dtype dt, const void *dA, int64
               perm_out ot, uint32_t flags, double fraction, int reps, void *stream, double *ms,
               double *fraction_run) {
   if (!ms || reps < 1 || !(fraction > 0.0 && fraction <= 1.0)) return PERM_E_INVALID;
-  if ((int)algo < 0 || (int)algo > (int)PERM_ALGO_GLYNN) return PERM_E_INVALID;
+  if ((int)algo < 0 || (int)algo > (int)PERM_ALGO_SWEEP || algo == PERM_ALGO_AUTO)
+    return PERM_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
   void *dOut = nullptr;
   if (hipMalloc(&dOut, 64) != hipSuccess) return PERM_E_HIP;
@@ -227,7 +230,7 @@ int perm_selector_save(const char *path, const float *hParams, const float *hNor
   if (!path || !hParams || !hNorm) return PERM_E_INVALID;
   FILE *f = std::fopen(path, "w");
   if (!f) return PERM_E_INVALID;
-  std::fprintf(f, "permgpu-selector 1\n");
+  std::fprintf(f, "permgpu-selector 2\n");
   if (hTable) {
     std::fprintf(f, "table");
     for (int i = 0; i < 8; ++i) std::fprintf(f, " %.9g", hTable[i]);

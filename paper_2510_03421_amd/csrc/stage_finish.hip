@@ -63,7 +63,8 @@ __global__ __launch_bounds__(kReduceThreads) void pad_scale_kernel(int m, int n,
 // for odd c).  g_start = 0 is the whole walk.
 __device__ __forceinline__ void update_entry(int algo, int m, perm_dtype dt, const void *dA,
                                              int64_t lda, int tr, double pad, int q, int j,
-                                             double &re, double &im) {
+                                             double &re, double &im,
+                                             const int32_t *col_order = nullptr) {
   if (algo != 1) {
     if (q + 1 < m) {
       read_entry(dt, dA, lda, tr, q + 1, j, re, im);
@@ -74,13 +75,14 @@ __device__ __forceinline__ void update_entry(int algo, int m, perm_dtype dt, con
     re *= -2.0;
     im *= -2.0;
   } else {
-    read_entry(dt, dA, lda, tr, j, q, re, im);
+    read_entry(dt, dA, lda, tr, j, col_order ? col_order[q] : q, re, im);
   }
 }
 
 __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const void *dA,
                                   int64_t lda, int tr, double *tbl, double *base, int C,
-                                  const int *pad_exp, uint64_t g_start) {
+                                  const int *pad_exp, uint64_t g_start,
+                                  const int32_t *col_order) {
   const double pad = pad_exp ? __builtin_ldexp(1.0, *pad_exp) : 1.0;
   const int nv = algo == 1 ? m : n;
   const int nbits = algo == 0 ? n - 1 : (algo == 1 ? n : m - 1);
@@ -88,7 +90,7 @@ __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const v
   if (idx < nbits * nv) {
     const int q = idx / nv, j = idx % nv;
     double re, im;
-    update_entry(algo, m, dt, dA, lda, tr, pad, q, j, re, im);
+    update_entry(algo, m, dt, dA, lda, tr, pad, q, j, re, im, col_order);
     if ((g_start >> q) & 1u) {
       re = -re;
       im = -im;
@@ -115,7 +117,7 @@ __global__ void stage_gray_kernel(int algo, int m, int n, perm_dtype dt, const v
     for (int q = 0; q < nbits; ++q) {
       if ((g_start >> q) & 1u) {
         double re, im;
-        update_entry(algo, m, dt, dA, lda, tr, pad, q, idx, re, im);
+        update_entry(algo, m, dt, dA, lda, tr, pad, q, idx, re, im, col_order);
         sr += re;
         si += im;
       }
@@ -335,14 +337,37 @@ hipError_t launch_pad_scale(int m, int n, perm_dtype dt, const void *dA, int64_t
 
 hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *dA, int64_t lda,
                              int tr, double *tbl, double *base, int cplx, hipStream_t s,
-                             const int *pad_exp, uint64_t g_start) {
+                             const int *pad_exp, uint64_t g_start, const int32_t *col_order) {
   const int nv = algo == 1 ? m : n;
   const int nbits = algo == 0 ? n - 1 : (algo == 1 ? n : m - 1);
   int work = nbits * nv > nv ? nbits * nv : nv;
   if (work < 1) work = 1;
   const int threads = 256, blocks = (work + threads - 1) / threads;
   hipLaunchKernelGGL(stage_gray_kernel, dim3(blocks), dim3(threads), 0, s, algo, m, n, dt, dA, lda,
-                     tr, tbl, base, cplx ? 2 : 1, pad_exp, g_start);
+                     tr, tbl, base, cplx ? 2 : 1, pad_exp, g_start, col_order);
+  return hipGetLastError();
+}
+
+// one thread per row: the bit mask of its nonzero entries
+__global__ void row_masks_kernel(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                                 uint64_t *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint64_t mask = 0;
+  for (int j = 0; j < n; ++j) {
+    double re, im;
+    read_entry(dt, dA, lda, tr, i, j, re, im);
+    if (re != 0.0 || im != 0.0) mask |= 1ull << j;
+  }
+  out[i] = mask;
+}
+
+hipError_t launch_row_masks(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                            uint64_t *out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int threads = 64, blocks = (m + threads - 1) / threads;
+  hipLaunchKernelGGL(row_masks_kernel, dim3(blocks), dim3(threads), 0, s, m, n, dt, dA, lda, tr,
+                     out);
   return hipGetLastError();
 }
 

@@ -2,8 +2,9 @@
 training, over the C ABI of ``libpermgpu.so`` (argument marshalling only).
 
 The network maps the features of a problem (log m, log n, density, dtype id;
-see ``features``) to predicted log run times of the three algorithms in
-``perm_algo`` order (combinatoric, Ryser, Glynn).
+see ``features``) to predicted log run times of five algorithms, in the order
+of ``ALGO_ORDER``: combinatoric, Ryser, Glynn, the e_m form (rectangular
+shapes), the column sweep.
 """
 from __future__ import annotations
 
@@ -17,7 +18,11 @@ from . import _capi as C
 from . import _DT, _OUT, _DEFAULT_OUT, _matrix, _stream, _ALGO_ID
 
 NPARAMS = C.PERM_MLP_PARAMS
-ALGO_ORDER = ("combinatoric", "ryser", "glynn")
+ALGO_ORDER = ("combinatoric", "ryser", "glynn", "glynn_esym", "column_sweep")
+NOUT = len(ALGO_ORDER)
+# perm_algo value of each network output
+ALGO_IDS = (C.PERM_ALGO_COMBINATORIC, C.PERM_ALGO_RYSER, C.PERM_ALGO_GLYNN,
+            C.PERM_ALGO_GLYNN_ESYM, C.PERM_ALGO_SWEEP)
 
 
 def features(m: int, n: int, dtype: torch.dtype, density: float = -1.0) -> np.ndarray:
@@ -51,9 +56,9 @@ def _dev(t: torch.Tensor, name: str) -> torch.Tensor:
 
 
 def mlp_forward(params: torch.Tensor, norm: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
-    """Network outputs y[batch][3] for features x[batch][4] (device float32)."""
+    """Network outputs y[batch][NOUT] for features x[batch][4] (device float32)."""
     _dev(params, "params"), _dev(norm, "norm"), _dev(x, "x")
-    y = torch.empty(x.shape[0], 3, dtype=torch.float32, device=x.device)
+    y = torch.empty(x.shape[0], NOUT, dtype=torch.float32, device=x.device)
     C.check(C.lib.perm_mlp_forward(params.data_ptr(), norm.data_ptr(), x.data_ptr(),
                                    x.shape[0], y.data_ptr(), _stream(x)), "perm_mlp_forward")
     return y
@@ -86,13 +91,13 @@ def mlp_adam(params, grad, state, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
 def train(x: np.ndarray, t: np.ndarray, epochs: int, lr: float = 3e-3, seed: int = 1,
           params: np.ndarray | None = None):
     """Full-batch training on the GPU (perm_selector_train).  x: float32[N][4]
-    features, t: float32[N][3] log times (NaN = unavailable).  Starts from
+    features, t: float32[N][NOUT] log times (NaN = unavailable).  Starts from
     ``params`` if given, else from the seeded initialisation.  Returns
     (params, norm, loss history)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     t = np.ascontiguousarray(t, dtype=np.float32)
-    if x.ndim != 2 or x.shape[1] != 4 or t.shape != (x.shape[0], 3):
-        raise ValueError("x must be [N][4] and t [N][3]")
+    if x.ndim != 2 or x.shape[1] != 4 or t.shape != (x.shape[0], NOUT):
+        raise ValueError(f"x must be [N][4] and t [N][{NOUT}]")
     init = params is None
     p = np.zeros(NPARAMS, dtype=np.float32) if init else \
         np.array(params, dtype=np.float32, copy=True)

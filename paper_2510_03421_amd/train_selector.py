@@ -28,7 +28,8 @@ from . import _capi as C
 from . import selector as S
 
 DTYPES = {"f64": torch.float64, "c128": torch.complex128, "b8": torch.uint8}
-COMB, RYSER, GLYNN = 0, 1, 2
+COMB, RYSER, GLYNN, ESYM, SWEEP = 0, 1, 2, 3, 4   # network output indices (S.ALGO_ORDER)
+OUT_OF_ALGO = {a: k for k, a in enumerate(S.ALGO_IDS)}
 
 
 def load_timings(path: str) -> dict:
@@ -38,7 +39,7 @@ def load_timings(path: str) -> dict:
     head, rows = rows[0], rows[1:]
     col = {h: i for i, h in enumerate(head)}
     get = lambda r, h: r[col[h]]
-    ms = np.array([[float(get(r, f"ms_{a}")) if get(r, f"ms_{a}") else np.nan
+    ms = np.array([[float(get(r, f"ms_{a}")) if f"ms_{a}" in col and get(r, f"ms_{a}") else np.nan
                     for a in S.ALGO_ORDER] for r in rows])
     return {
         "i": np.array([int(get(r, "i")) for r in rows]),
@@ -86,32 +87,57 @@ def library_choices(d: dict, idx, weights: str | None) -> np.ndarray:
                                    "b8": C.PERM_B8}[d["dtype"][i]],
                                   float(d["density"][i]), ctypes.byref(ch), ctypes.byref(src)),
                 "perm_select")
-        out[k] = ch.value
+        out[k] = OUT_OF_ALGO[ch.value]
     return out
 
 
 # ---- the threshold table (Alg. 5's form), for fitting ----
 def log2_terms(m: np.ndarray, n: np.ndarray) -> np.ndarray:
-    """log2 of the term counts (combinatoric, Ryser, Glynn) per case."""
+    """log2 of the term counts per case of the five algorithms (combinatoric,
+    Ryser, Glynn, the e_m form, the column sweep's state updates), as the
+    library ranks them (log2_algo_terms)."""
     lc = np.array([sum(math.log2(nn - i) for i in range(mm)) for mm, nn in zip(m, n)])
     lr = np.array([float(nn) if mm == nn else
                    math.log2(sum(math.comb(int(nn), k) for k in range(int(mm) + 1)))
                    for mm, nn in zip(m, n)])
-    return np.stack([lc, lr, n - 1.0], axis=1)
+    le = m - 1.0
+    ls = []
+    for mm, nn in zip(m, n):
+        mm, nn = int(mm), int(nn)
+        tot = sum(math.comb(mm, k) * max(0, min(nn - mm + 1, k + 1, nn - (mm - k)))
+                  for k in range(mm + 1))
+        ls.append(math.log2(max(tot, 1)))
+    return np.stack([lc, lr, n - 1.0, le, np.array(ls)], axis=1)
+
+
+def log2_ops(m: np.ndarray, n: np.ndarray, terms: np.ndarray) -> np.ndarray:
+    """log2 of the rough operation counts the library's table rule compares
+    (terms times the work of one term)."""
+    mm, nn = m.astype(float), n.astype(float)
+    per = np.stack([np.maximum(mm, 1), 2 * mm, 2 * nn, nn * (np.minimum(mm, 32) + 1),
+                    np.maximum(mm, 1)], axis=1)
+    return terms + np.log2(per)
 
 
 def table_choice(p: np.ndarray, m: np.ndarray, n: np.ndarray, avail: np.ndarray,
                  terms: np.ndarray) -> np.ndarray:
-    """Alg. 5's decision with values p[1..8], then the first available
-    algorithm with the table's choice first and the rest by term count."""
+    """The library's table policy: Alg. 5's decision with values p[1..8]
+    among the paper's three algorithms, the e_m form instead when its
+    operation count is below half of that choice's, the rest by term count
+    with the column sweep last; the first available algorithm."""
     r = m / n
     small = n <= p[8]
     comb_small = ((m == n) & (n <= p[4])) | (p[1] * r + p[2] * n + p[3] > 0)
     glynn_large = p[5] * r + p[6] * n + p[7] > 0
     pick = np.where(small, np.where(comb_small, COMB, GLYNN),
                     np.where(glynn_large, GLYNN, RYSER))
+    rows = np.arange(len(pick))
+    ops = log2_ops(m, n, terms)
+    esym = avail[:, ESYM] & (ops[:, ESYM] + 1.0 < ops[rows, pick])
+    pick = np.where(esym, ESYM, pick)
     key = terms.copy()
-    key[np.arange(len(pick)), pick] = -1e300
+    key[rows, pick] = -1e300
+    key[:, SWEEP] = 1e300
     key = np.where(avail, key, np.inf)
     return np.argmin(key, axis=1)
 
@@ -172,7 +198,7 @@ def main(argv=None) -> int:
 
     table_only = os.path.join(tmp, "table.txt")
     with open(table_only, "w") as fh:
-        fh.write("permgpu-selector 1\ntable " + " ".join(f"{v:.9g}" for v in table[1:]) + "\n")
+        fh.write("permgpu-selector 2\ntable " + " ".join(f"{v:.9g}" for v in table[1:]) + "\n")
     pol = {
         "mlp": library_choices(d, te, args.out),
         "table_fitted": library_choices(d, te, table_only),
@@ -181,6 +207,9 @@ def main(argv=None) -> int:
     avail = ~np.isnan(ms_te)
     glynn_first = np.where(avail[:, GLYNN], GLYNN, np.where(avail[:, RYSER], RYSER, COMB))
     pol["always_glynn"] = glynn_first
+    # the paper's three algorithms only (no e_m form, no sweep): best of them
+    three = np.where(avail[:, :3], ms_te[:, :3], np.inf)
+    pol["best_of_three"] = np.argmin(three, axis=1)
     rep = {"cases": int(len(d["m"])), "train": int(len(tr)), "held_out": int(len(te)),
            "epochs": args.epochs, "lr": args.lr, "seed": sd,
            "loss_first": float(hist[0]), "loss_last": float(hist[-1]),

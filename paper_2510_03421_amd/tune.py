@@ -32,8 +32,8 @@ if _ROOT not in sys.path:
     sys.path.insert(0, _ROOT)
 import workloads  # noqa: E402  (seeded case recipes)
 
-HEADER = "i,m,n,dtype,density,seed,ms_combinatoric,ms_ryser,ms_glynn,frac_combinatoric," \
-         "frac_ryser,frac_glynn,s_combinatoric,s_ryser,s_glynn"
+HEADER = "i,m,n,dtype,density,seed," + ",".join(
+    f"{k}_{a}" for k in ("ms", "frac", "s") for a in S.ALGO_ORDER)
 TORCH_DT = {"f64": torch.float64, "c128": torch.complex128, "b8": torch.uint8}
 SLOPE_MS = 3.0       # the cut-down run used for the slope adds at least this much
 FULL_MS = 25.0       # whole runs shorter than this are timed again with more repetitions

@@ -12,6 +12,9 @@ independent evaluator: for the Glynn-evaluated inputs (32x32 real and complex,
 Eq. ryser_square), which shares no seeding or update step with the Glynn walk
 over row signs; the tests check that the two agree within their error bounds.
 Set ``ORACLE_THREADS`` to limit the threads used.
+
+``--batches`` writes tests/golden/batch_reference.json: the oracle's values of
+the first matrices of the benchmark's batched workloads.
 """
 import json
 import os
@@ -84,9 +87,38 @@ def main(names, second=False):
         os.replace(OUT + ".tmp", OUT)
 
 
+BATCH_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch_reference.json")
+
+
+def batches(sample: int = 400):
+    """Reference permanents of the first `sample` matrices of the benchmark's
+    two batches: the 200,000 Haar submatrices (complex double-double Glynn)
+    and the 20,000 0/1 matrices (exact, memoised expansion)."""
+    out = {}
+    b = workloads.boson_batch(200_000, 4, 20, N=64, seed_u=6400, seed_idx=6401)
+    vals = []
+    for i in range(sample):
+        v = oracle.per_glynn(np.ascontiguousarray(b.matrix(i)))
+        vals.append([v.re.hi, v.re.lo, v.im.hi, v.im.lo])
+    out["boson_200000_c128_n4..20"] = {"recipe": "workloads.boson_batch(200000, 4, 20, N=64, "
+                                       "seed_u=6400, seed_idx=6401)", "evaluator": "glynn",
+                                       "first": sample, "values": vals}
+    z = workloads.bernoulli_batch(20_000, 8, 24, 0.5, seed=6500)
+    ints = [str(oracle.per_laplace(np.ascontiguousarray(z.matrix(i)).astype(np.int64)))
+            for i in range(sample)]
+    out["bernoulli_20000_b8_n8..24"] = {"recipe": "workloads.bernoulli_batch(20000, 8, 24, 0.5, "
+                                        "seed=6500)", "evaluator": "laplace", "first": sample,
+                                        "values": ints}
+    with open(BATCH_OUT + ".tmp", "w") as fh:
+        json.dump(out, fh)
+    os.replace(BATCH_OUT + ".tmp", BATCH_OUT)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     if args and args[0] == "--second":
         main(args[1:] or ["u32", "c32", "u36"], second=True)
+    elif args and args[0] == "--batches":
+        batches()
     else:
         main(args or ["u12", "b16x48", "u20x40", "b28", "u32", "b30", "c32"])

@@ -193,3 +193,17 @@ def test_triangular_within_formula_bound(n):
     U = 2.0 ** -53
     assert abs(run_algo("glynn", dev(t)) - exact) <= 4 * n * U * glynn_abs + 4 * n * U * abs(exact)
     assert abs(run_algo("ryser", dev(t)) - exact) <= 4 * n * U * ryser_abs + 4 * n * U * abs(exact)
+
+
+@pytest.mark.parametrize("n,p,seed", [(14, 0.15, 1), (18, 0.12, 2), (22, 0.2, 3), (24, 0.1, 4),
+                                      (26, 0.15, 5), (20, 0.5, 6)])
+def test_sparse_01_ryser_exact(n, p, seed):
+    """Sparse 0/1 square matrices (the rows reordered by their counts of
+    ones, whole waves of zero terms skipped) stay bit-exact."""
+    import oracle
+    a = workloads.bernoulli(n, n, p, 3300 + seed)
+    want = oracle.per_laplace(a.astype(np.int64))
+    assert run_algo("ryser", dev(a)) == want
+    assert run_algo("ryser", dev(np.ascontiguousarray(a.T))) == want
+    import paper_2510_03421_amd as pg
+    assert pg.ryser(dev(a), flags=pg._capi.PERM_FLAG_WRAP).value() == want

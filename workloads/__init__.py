@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "uniform", "complex_gauss", "bernoulli", "haar_unitary", "cauchy_dyadic",
-    "boson_batch", "selector_cases", "BatchSpec", "CONFIGS", "config_matrix",
+    "boson_batch", "bernoulli_batch", "selector_cases", "BatchSpec", "CONFIGS", "config_matrix",
 ]
 
 
@@ -106,6 +106,22 @@ def boson_batch(count: int, nmin: int, nmax: int, N: int = 64, seed_u: int = 640
         rows = np.sort(rng.choice(N, size=k, replace=False))
         cols = np.sort(rng.choice(N, size=k, replace=False))
         data[offs[b]:offs[b] + k * k] = U[np.ix_(rows, cols)].reshape(-1)
+    return BatchSpec(data=data, m=ns.copy(), n=ns, offset=offs, ld=ns.astype(np.int64))
+
+
+def bernoulli_batch(count: int, nmin: int, nmax: int, p: float = 0.5,
+                    seed: int = 6500) -> BatchSpec:
+    """``count`` square 0/1 matrices (uint8) of orders n_b ~ U{nmin..nmax},
+    each entry 1 with probability p (bipartite graphs whose perfect matchings
+    the permanent counts), packed contiguously with ld = n_b."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(nmin, nmax + 1, size=count).astype(np.int32)
+    offs = np.zeros(count, dtype=np.int64)
+    total = 0
+    for b in range(count):
+        offs[b] = total
+        total += int(ns[b]) * int(ns[b])
+    data = (rng.random(size=total) < p).astype(np.uint8)
     return BatchSpec(data=data, m=ns.copy(), n=ns, offset=offs, ld=ns.astype(np.int64))
 
 
