@@ -251,41 +251,56 @@ int int_prod_selector(const std::vector<uint64_t> &bounds) {
   return 0;
 }
 
-static int read_abs_sums(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                         int by_cols, std::vector<uint64_t> &out, hipStream_t s) {
-  const int count = (by_cols == 1 || by_cols == 3) ? N : M;
-  out.assign(count, 0);
+// Row and column magnitudes and row nonzero masks (launch_int_stats), read
+// back in one round trip.
+struct IntStats {
+  std::vector<uint64_t> rows, cols, sq_rows, sq_cols, masks;
+};
+static int read_int_stats(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                          IntStats &st, hipStream_t s) {
+  const size_t cnt = 2 * (size_t)(M + N) + (size_t)M;
+  std::vector<uint64_t> h(cnt, 0);
   uint64_t *d = nullptr;
-  if (hipMallocAsync((void **)&d, sizeof(uint64_t) * (size_t)count, s) != hipSuccess)
+  if (hipMallocAsync((void **)&d, sizeof(uint64_t) * std::max<size_t>(cnt, 1), s) != hipSuccess)
     return PERM_E_HIP;
-  hipError_t e = launch_abs_sums(M, N, dt, dA, lda, tr, by_cols, d, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(out.data(), d, sizeof(uint64_t) * (size_t)count, hipMemcpyDeviceToHost, s);
+  hipError_t e = launch_int_stats(M, N, dt, dA, lda, tr, d, s);
+  if (e == hipSuccess && cnt)
+    e = hipMemcpyAsync(h.data(), d, sizeof(uint64_t) * cnt, hipMemcpyDeviceToHost, s);
   hipError_t e2 = hipFreeAsync(d, s);
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+  if (e != hipSuccess) return PERM_E_HIP;
+  const auto at = h.begin();
+  st.rows.assign(at, at + M);
+  st.cols.assign(at + M, at + M + N);
+  st.sq_rows.assign(at + M + N, at + 2 * M + N);
+  st.sq_cols.assign(at + 2 * M + N, at + 2 * (M + N));
+  st.masks.assign(at + 2 * (M + N), at + 2 * (M + N) + M);
+  return PERM_OK;
 }
 
 // Fills `pl` and checks overflow for an integer run of `algo` (0 Glynn,
 // 1 Ryser square/rect, 2 the e_m form) on the logical M x N matrix.
 int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                 perm_out ot, uint32_t flags, hipStream_t s, int &pl) {
+                 perm_out ot, uint32_t flags, hipStream_t s, int &pl,
+                 std::vector<uint64_t> *row_masks) {
   const bool wrap = (flags & PERM_FLAG_WRAP) != 0;
-  std::vector<uint64_t> rows, cols;
+  IntStats st;
+  // one read of every magnitude (0/1 input under PERM_FLAG_WRAP needs none,
+  // unless the caller wants the nonzero masks)
+  if (!(dt == PERM_B8 && wrap) || row_masks) {
+    int rc = read_int_stats(M, N, dt, dA, lda, tr, st, s);
+    if (rc) return rc;
+    if (row_masks) *row_masks = st.masks;
+  }
+  std::vector<uint64_t> &rows = st.rows, &cols = st.cols;
   if (dt == PERM_B8 && wrap) {
+    // the bounds from the shape alone
     rows.assign(M, (uint64_t)N);
     cols.assign(N, (uint64_t)N);
-  } else {
-    int rc = read_abs_sums(M, N, dt, dA, lda, tr, 0, rows, s);
-    if (rc) return rc;
-    if (algo == 0 || algo == 2) {
-      rc = read_abs_sums(M, N, dt, dA, lda, tr, 1, cols, s);
-      if (rc) return rc;
-      if (algo == 0)  // the padding rows of ones
-        for (auto &c : cols) c = (c > ~0ull - (uint64_t)N) ? ~0ull : c + (uint64_t)(N - M);
-    }
   }
+  if (algo == 0)  // the padding rows of ones
+    for (auto &c : cols) c = (c > ~0ull - (uint64_t)N) ? ~0ull : c + (uint64_t)(N - M);
   // Glynn and Ryser form binary64 chunk products; the e_m form only needs
   // every column sum exact in binary64 (the selector is < 0 iff one is not)
   pl = int_prod_selector(algo == 1 ? rows : cols);
@@ -304,10 +319,7 @@ int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t 
   if (M == N) {
     // Carlen-Lieb-Loss: |per(A)| <= n!/n^(n/2) prod_j ||a_j||_2 over the columns
     // (and, applied to A^T, over the rows)
-    std::vector<uint64_t> sq_rows, sq_cols;
-    int rc = read_abs_sums(M, N, dt, dA, lda, tr, 2, sq_rows, s);
-    if (!rc) rc = read_abs_sums(M, N, dt, dA, lda, tr, 3, sq_cols, s);
-    if (rc) return rc;
+    const std::vector<uint64_t> &sq_rows = st.sq_rows, &sq_cols = st.sq_cols;
     const double base = std::lgamma((double)N + 1.0) / std::log(2.0) -
                         0.5 * (double)N * std::log2((double)N);
     double lr = base, lc = base;
@@ -395,21 +407,6 @@ struct RyserWindow {
   uint64_t wblocks = 0;            // states << wlow
   GrayPlan plan;
 };
-
-static int read_row_masks(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                          std::vector<uint64_t> &out, hipStream_t s) {
-  out.assign(M, 0);
-  uint64_t *d = nullptr;
-  if (hipMallocAsync((void **)&d, sizeof(uint64_t) * (size_t)std::max(M, 1), s) != hipSuccess)
-    return PERM_E_HIP;
-  hipError_t e = launch_row_masks(M, N, dt, dA, lda, tr, d, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(out.data(), d, sizeof(uint64_t) * (size_t)M, hipMemcpyDeviceToHost, s);
-  hipError_t e2 = hipFreeAsync(d, s);
-  if (e == hipSuccess) e = e2;
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
-}
 
 // Relative time of an engine walk: blocks per lane times one block (2^b
 // steps of an update and a product over nv entries, plus the closed-form
@@ -541,25 +538,26 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
                      : kind == ENGINE_CPLX ? ENGINE_MAX_NV_CPLX
                                            : ENGINE_MAX_NV_INT;
   if (nv > nv_max) return PERM_E_TOO_LARGE;
+  // exact square Ryser over the whole walk: prune the column subsets that
+  // leave a sparse row empty (the nonzero masks come with the pre-check)
+  // PERM_RYSER_WINDOW: 0 = always the whole walk, 2 = a window whenever one
+  // prunes (for tests at orders where the model keeps the whole walk)
+  const int win_mode = env_int("PERM_RYSER_WINDOW", 1);
+  const bool try_win = kind == ENGINE_INT && algo == 1 && chunk_log2 < 0 && nbits >= 3 &&
+                       win_mode != 0;
+  std::vector<uint64_t> masks;
   int pl = 3;
   if (kind == ENGINE_INT) {
-    int rc = int_precheck(algo, M, N, dt, dA, lda, tr, ot, flags, s, pl);
+    int rc = int_precheck(algo, M, N, dt, dA, lda, tr, ot, flags, s, pl,
+                          try_win ? &masks : nullptr);
     if (rc) return rc;
   }
   GrayPlan plan;
   int rc = plan_gray(kind, nv, nbits, plan);
   if (rc) return rc;
-  // exact square Ryser over the whole walk: prune the column subsets that
-  // leave a sparse row empty (the host already waits for the pre-check here)
   RyserWindow win;
   bool use_win = false;
-  // PERM_RYSER_WINDOW: 0 = always the whole walk, 2 = a window whenever one
-  // prunes (for tests at orders where the model keeps the whole walk)
-  const int win_mode = env_int("PERM_RYSER_WINDOW", 1);
-  if (kind == ENGINE_INT && algo == 1 && chunk_log2 < 0 && nbits >= 3 && win_mode != 0) {
-    std::vector<uint64_t> masks;
-    rc = read_row_masks(M, N, dt, dA, lda, tr, masks, s);
-    if (rc) return rc;
+  if (try_win) {
     const uint64_t lanes_max =
         pow2_floor((uint64_t)device_cus() * (uint64_t)gray_engine_blocks_per_cu_int(nv) * 256u);
     use_win = plan_ryser_window(masks, N, lanes_max, win_mode == 2, win);

@@ -198,9 +198,6 @@ hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *
                              int tr, double *tbl, double *base, int cplx, hipStream_t s,
                              const int *pad_exp = nullptr, uint64_t g_start = 0,
                              const int32_t *col_order = nullptr);
-// out[i] = bit mask of the nonzero entries of row i (n <= 64).
-hipError_t launch_row_masks(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                            uint64_t *out, hipStream_t s);
 // The exponent of the floating-point Glynn padding value (device int *e).
 hipError_t launch_pad_scale(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
                             int *e, hipStream_t s);
@@ -248,11 +245,12 @@ int esym_blocks_per_cu_int(int nv);
 hipError_t launch_finish(int kind, const void *partials, int count, const Finish &f, void *dOut,
                          hipStream_t s);
 
-// Magnitudes of each logical row (by_cols = 0) or column (1) of an integer
-// matrix: absolute sums, exact, saturating at 2^64 - 1; by_cols = 2 / 3: sums
-// of squares of each row / column as doubles (bit patterns).
-hipError_t launch_abs_sums(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                           int by_cols, uint64_t *dSums, hipStream_t s);
+// Magnitudes of the logical rows and columns of an integer matrix, in one
+// pass: out[0 .. m+n) absolute sums (rows, then columns; exact, saturating
+// at 2^64 - 1), out[m+n .. 2(m+n)) sums of squares (bit patterns of
+// doubles), out[2(m+n) .. 2(m+n)+m) each row's nonzero mask (columns < 64).
+hipError_t launch_int_stats(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                            uint64_t *out, hipStream_t s);
 
 // Rectangular Ryser staging (column table and difference columns) and engine.
 hipError_t launch_stage_rect(int m, int n, int l, perm_dtype dt, const void *dA, int64_t lda,

@@ -40,7 +40,8 @@ int validate(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out 
              int &kind);
 int int_prod_selector(const std::vector<uint64_t> &bounds);
 int int_precheck(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                 perm_out ot, uint32_t flags, hipStream_t s, int &pl);
+                 perm_out ot, uint32_t flags, hipStream_t s, int &pl,
+                 std::vector<uint64_t> *row_masks = nullptr);
 
 // Runners on the logical M x N matrix (M <= N; tr = read A^T).
 // chunk_log2 < 0: the whole walk; else the chunk of 2^chunk_log2 Gray indices

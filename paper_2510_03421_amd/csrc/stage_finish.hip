@@ -254,17 +254,22 @@ __global__ __launch_bounds__(kReduceThreads) void finish_kernel(int kind, const 
 // Per-line magnitudes of an integer matrix.  mode 0: absolute sum of each
 // logical row, 1: of each column (exact in 64 bits, saturating); mode 2 / 3:
 // sum of squares of each row / column as a double (bit pattern in the slot).
-__global__ void abs_sums_kernel(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                                int mode, uint64_t *sums) {
+// One thread per logical row (idx < m) or column (idx = m + j) of an integer
+// matrix: its absolute sum (exact, saturating at 2^64 - 1) and its sum of
+// squares (a double's bit pattern); a row also gets the bit mask of its
+// nonzero entries (columns below 64).  Layout of `out`: abs[m + n],
+// sq[m + n], masks[m].
+__global__ void int_stats_kernel(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                                 uint64_t *out) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool by_cols = mode == 1 || mode == 3;
-  const int count = by_cols ? n : m;
-  if (idx >= count) return;
-  const int len = by_cols ? m : n;
+  if (idx >= m + n) return;
+  const bool col = idx >= m;
+  const int len = col ? m : n;
   u128 s = 0;
   double q = 0.0;
+  uint64_t mask = 0;
   for (int k = 0; k < len; ++k) {
-    const int i = by_cols ? k : idx, j = by_cols ? idx : k;
+    const int i = col ? k : idx, j = col ? idx - m : k;
     const int64_t o = tr ? (int64_t)j * lda + i : (int64_t)i * lda + j;
     int64_t x;
     if (dt == PERM_I64) x = ((const int64_t *)dA)[o];
@@ -272,9 +277,11 @@ __global__ void abs_sums_kernel(int m, int n, perm_dtype dt, const void *dA, int
     s += x < 0 ? (u128)(-(i128)x) : (u128)x;
     const double xd = (double)x;
     q = __builtin_fma(xd, xd, q);
+    if (x != 0 && k < 64) mask |= 1ull << k;
   }
-  if (mode >= 2) sums[idx] = (uint64_t)__double_as_longlong(q);
-  else sums[idx] = (s >> 64) ? ~0ull : (uint64_t)s;
+  out[idx] = (s >> 64) ? ~0ull : (uint64_t)s;
+  out[m + n + idx] = (uint64_t)__double_as_longlong(q);
+  if (!col) out[2 * (m + n) + idx] = mask;
 }
 
 __global__ void write_one_kernel(perm_out ot, void *out) {
@@ -348,28 +355,6 @@ hipError_t launch_stage_gray(int algo, int m, int n, perm_dtype dt, const void *
   return hipGetLastError();
 }
 
-// one thread per row: the bit mask of its nonzero entries
-__global__ void row_masks_kernel(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                                 uint64_t *out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  uint64_t mask = 0;
-  for (int j = 0; j < n; ++j) {
-    double re, im;
-    read_entry(dt, dA, lda, tr, i, j, re, im);
-    if (re != 0.0 || im != 0.0) mask |= 1ull << j;
-  }
-  out[i] = mask;
-}
-
-hipError_t launch_row_masks(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                            uint64_t *out, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  const int threads = 64, blocks = (m + threads - 1) / threads;
-  hipLaunchKernelGGL(row_masks_kernel, dim3(blocks), dim3(threads), 0, s, m, n, dt, dA, lda, tr,
-                     out);
-  return hipGetLastError();
-}
 
 hipError_t launch_gray_tiny(int kind, const GrayWalk &w, void *partials, hipStream_t s) {
   hipLaunchKernelGGL(gray_tiny_kernel, dim3(1), dim3(64), 0, s, kind, w.tbl, w.base, w.nv, w.nbits,
@@ -384,11 +369,12 @@ hipError_t launch_finish(int kind, const void *partials, int count, const Finish
   return hipGetLastError();
 }
 
-hipError_t launch_abs_sums(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
-                           int by_cols, uint64_t *dSums, hipStream_t s) {
-  const int count = (by_cols == 1 || by_cols == 3) ? n : m;
-  hipLaunchKernelGGL(abs_sums_kernel, dim3((count + 63) / 64), dim3(64), 0, s, m, n, dt, dA, lda,
-                     tr, by_cols, dSums);
+hipError_t launch_int_stats(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                            uint64_t *out, hipStream_t s) {
+  const int count = m + n;
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(int_stats_kernel, dim3((count + 63) / 64), dim3(64), 0, s, m, n, dt, dA, lda,
+                     tr, out);
   return hipGetLastError();
 }
 
