@@ -434,8 +434,9 @@ int perm_selector_features(int m, int n, perm_dtype dt, double density, float *x
  * lane (never fewer than two), in rectangular Ryser every wave stops after
  * that fraction of its share of the work (its last item's walks cut short),
  * the combinatoric sum runs whole rounds of its map prefixes (at least one),
- * so its x can differ from `fraction` by a round, and the column sweep runs
- * its first columns up to about that share of its state updates.  algo is
+ * so its x can differ from `fraction` by a round, and the column sweep always
+ * runs whole (x = 1: its cost is bounded, at most about 0.2 s, while its
+ * first columns, the cheapest, would leave only its fixed costs).  algo is
  * any perm_algo but PERM_ALGO_AUTO.  *fraction_run (may be NULL)
  * receives the fraction x actually run.  The value computed
  * is discarded.  Errors: those of the algorithm's entry point, and

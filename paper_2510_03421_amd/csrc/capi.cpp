@@ -736,18 +736,6 @@ int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, p
 // ------------------------------------------------------------------ //
 // the column sweep                                                    //
 // ------------------------------------------------------------------ //
-// State updates of column j of an m-row sweep over n columns: the states of
-// the sizes in its band, each reading one entry per row in it.
-double sweep_column_work(int m, int n, int j) {
-  const int lo = std::max(0, m - (n - 1 - j)), hi = std::min(j + 1, m);
-  double w = 0.0, c = 1.0;  // c = C(m, k)
-  for (int k = 0; k <= m; ++k) {
-    if (k >= lo && k <= hi) w += c * (double)(k + 1);
-    c = c * (double)(m - k) / (double)(k + 1);
-  }
-  return w;
-}
-
 int run_sweep(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
               void *dOut, uint32_t flags, hipStream_t s, int kind) {
   if (M > SWEEP_MAX_M) return PERM_E_TOO_LARGE;
@@ -759,22 +747,11 @@ int run_sweep(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, 
     if (rc == PERM_E_OVERFLOW && (flags & PERM_FLAG_WRAP)) rc = PERM_OK;
     if (rc) return rc;
   }
-  // perm_time: the first columns holding about the requested share of the work
-  int ncols = N;
-  const double f = tune_fraction();
-  if (f < 1.0) {
-    double total = 0.0;
-    for (int j = 0; j < N; ++j) total += sweep_column_work(M, N, j);
-    double acc = 0.0;
-    ncols = 0;
-    while (ncols < N && acc < f * total) acc += sweep_column_work(M, N, ncols++);
-    ncols = std::max(ncols, 1);
-    acc = 0.0;
-    for (int j = 0; j < ncols; ++j) acc += sweep_column_work(M, N, j);
-    tune_record(acc / total);
-  } else {
-    tune_record(1.0);
-  }
+  // perm_time runs the sweep whole: its cost is bounded (at most 28 rows,
+  // about 0.2 s), and a cut through its first columns -- the cheapest ones,
+  // the state band still narrow -- leaves only the fixed costs to time
+  const int ncols = N;
+  tune_record(1.0);
   const size_t sb = kind == ENGINE_REAL ? 8 : 16;
   const size_t bytes = sb << M;
   char *buf = nullptr;

@@ -56,7 +56,6 @@ int run_combinatoric(int M, int N, perm_dtype dt, const void *dA, int64_t lda, i
                      perm_out ot, void *dOut, uint32_t flags, hipStream_t s, int kind);
 int run_sweep(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
               void *dOut, uint32_t flags, hipStream_t s, int kind);
-double sweep_column_work(int m, int n, int j);
 int run_esym(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr, perm_out ot,
              void *dOut, uint32_t flags, hipStream_t s, int kind);
 int release_rect_tables(int dev);

@@ -195,15 +195,13 @@ def test_perm_time_cuts_work_and_restores_it():
     with pytest.raises(pg.PermError):
         S.time("combinatoric", a)                 # 34! maps: refused by size
     # the e_m form cuts its Gray blocks (when each lane walks several: 2^31
-    # sign vectors here, at least two blocks per lane still run), the column
-    # sweep its columns
+    # sign vectors here, at least two blocks per lane still run); the column
+    # sweep always runs whole (its cost is bounded)
     _, fe = S.time("glynn_esym", cu(rng.uniform(-1, 1, size=(32, 48))), fraction=0.01, reps=1)
     assert 0 < fe <= 0.5
     e = cu(rng.uniform(-1, 1, size=(24, 40)))
     _, fs = S.time("column_sweep", e, fraction=0.3, reps=1)
-    assert 0 < fs < 0.6
-    _, fs1 = S.time("column_sweep", e, fraction=1.0, reps=1)
-    assert fs1 == 1.0
+    assert fs == 1.0
 
 
 def test_auto_moves_on_when_glynn_refuses_an_integer_bound():
