@@ -189,8 +189,12 @@ int perm_glynn_noalloc(int m, int n, perm_dtype dt, const void *dA, int64_t lda,
  *   c_j = sum_i delta_i a_ij,
  * with e_m the m-th elementary symmetric polynomial of c_1..c_n (expanding
  * e_m into row choices, the sign sum keeps the products that use every row
- * once).  Cost 2^(m-1) terms of O(n min(m, 32)) instead of Glynn's 2^(n-1)
- * terms for m < n.  Integer outputs are exact (the degrees are kept modulo
+ * once).  Cost 2^(m-1) terms instead of Glynn's 2^(n-1) for m < n; a term
+ * runs the recurrence e_k += c_j e_(k-1) over the columns, for floating-point
+ * outputs at 14 <= m <= 32 only over the degrees that can still reach e_m
+ * (max(1, j+1-(n-m)) <= k <= min(j+1, m) at column j: about m (n-m+1)
+ * multiply-adds), otherwise over every degree up to min(n, 32).  Integer
+ * outputs are exact (the degrees are kept modulo
  * 2^128, with the overflow pre-check of the integer paths: every column
  * absolute sum below 2^53 and |per| 2^(m-1) below 2^127, unless
  * PERM_FLAG_WRAP).  Limits: min(m, n) <= 32, max(m, n) <= 48. */

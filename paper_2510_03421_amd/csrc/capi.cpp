@@ -186,7 +186,14 @@ double esym_term_ops(int kind, int n, int m, bool band) {
 // The e_m walk's plan: the block length 2^b that minimises the estimated
 // time, (waves per SIMD) x (blocks per lane) x (seed + 2^b terms), with the
 // seed costing seed_ops per Gray bit at or above b-1.  Short walks thus keep
-// every SIMD busy with short blocks; long ones amortise the seeds.
+// every SIMD busy with short blocks; long ones amortise the seeds.  b = 0
+// (one term per block, each lane its own seed; the kernel signs a block's
+// first term by the parity of its index) may take one block per lane;
+// longer blocks pair blocks of opposite parity, two or more per lane.
+static uint64_t esym_lanes(uint64_t lanes_max, uint64_t L, int b) {
+  if (L == 1) return 1;
+  return std::min<uint64_t>(lanes_max, b == 0 ? L : L / 2);
+}
 int plan_esym(int bpc, int nbits, double term_ops, double seed_ops, GrayPlan &p) {
   const int cus = device_cus();
   if (bpc <= 0 || cus <= 0) return PERM_E_HIP;
@@ -194,24 +201,24 @@ int plan_esym(int bpc, int nbits, double term_ops, double seed_ops, GrayPlan &p)
   const double simds = 4.0 * cus;
   int best_b = 0;
   double best = 0.0;
-  for (int b = nbits == 0 ? 0 : 1; b <= std::min(nbits, 12); ++b) {
+  for (int b = 0; b <= std::min(nbits, 12); ++b) {
     const uint64_t L = 1ull << (nbits - b);
-    const uint64_t lanes = L == 1 ? 1 : std::min<uint64_t>(lanes_max, L / 2);
+    const uint64_t lanes = esym_lanes(lanes_max, L, b);
     const double bpl = (double)(L / lanes);
     const double waves = std::ceil((double)lanes / 64.0);
     const double wps = std::ceil(waves / simds);
     const double cost =
         wps * bpl * ((double)(nbits - std::max(b - 1, 0)) * seed_ops + (double)(1ull << b) * term_ops);
-    if (b == (nbits == 0 ? 0 : 1) || cost <= best) {
+    if (b == 0 || cost <= best) {
       best = cost;
       best_b = b;
     }
   }
   const int bo = env_int("PERM_ESYM_BLOCK_LOG2", -1);
-  if (bo >= 1 && bo <= nbits) best_b = bo;
+  if (bo >= 0 && bo <= nbits) best_b = bo;
   const uint64_t L = 1ull << (nbits - best_b);
   p.b = best_b;
-  p.lanes = L == 1 ? 1 : std::min<uint64_t>(lanes_max, L / 2);
+  p.lanes = esym_lanes(lanes_max, L, best_b);
   p.blocks_per_lane = L / p.lanes;
   p.block = (int)std::min<uint64_t>(256, p.lanes);
   p.grid = (int)(p.lanes / (uint64_t)p.block);

@@ -175,20 +175,37 @@ struct ELane<NV, 2> {
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] += row[j];
   }
+  // Only the degrees that can still reach e_m are updated: at column j,
+  // max(1, j + 1 - (NV - m)) <= k <= min(j + 1, m).  m is the same in every
+  // lane of the wave, so the tests are scalar branches around the 128-bit
+  // multiply-adds they skip (about a third of them remain at 16 x 48).
+  // The column sums are below 2^52 in magnitude (the pre-check), so each
+  // multiply-add is e_k +- |c_j| e_(k-1): a 128 x 52-bit product in 32-bit
+  // limbs (mul128x52) with the sign of c_j applied once per column.
   __device__ __forceinline__ u128 esym() const {
+    const int mu = __builtin_amdgcn_readfirstlane(m);
     u128 e[MV + 1];
     e[0] = 1;
 #pragma unroll
     for (int k = 1; k <= MV; ++k) e[k] = 0;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-      const u128 c = (u128)(i128)f64_to_i64_exact(v[j]);
+      const int64_t ci = f64_to_i64_exact(v[j]);
+      const uint64_t a = ci < 0 ? (uint64_t)0 - (uint64_t)ci : (uint64_t)ci;
+      const u128 neg = (u128)(i128)(ci >> 63);  // all ones if c_j < 0
 #pragma unroll
-      for (int k = (j + 1 < MV ? j + 1 : MV); k >= 1; --k) e[k] += c * e[k - 1];
+      for (int k = (j + 1 < MV ? j + 1 : MV); k >= 1; --k)
+        if (k <= mu && k >= j + 1 - (NV - mu)) {
+          uint64_t lo = (uint64_t)e[k - 1], hi = (uint64_t)(e[k - 1] >> 64);
+          mul128x52(lo, hi, a);
+          const u128 t = (((u128)hi << 64) | lo) ^ neg;
+          e[k] += t - neg;
+        }
     }
-    u128 r = e[MV];
+    u128 r = e[1];
 #pragma unroll
-    for (int k = MV - 1; k >= 1; --k) r = (k == m) ? e[k] : r;
+    for (int k = 2; k <= MV; ++k)
+      if (k == mu) r = e[k];
     return r;
   }
   __device__ __forceinline__ void term(bool neg) {
@@ -400,7 +417,9 @@ __global__ __launch_bounds__(kEsymBlock, WPE) void esym_walk_kernel(GrayWalk w, 
     L.load_base(w.base);
     const uint64_t g0 = k0 ^ (k0 >> 1);
     for (int q = qstart; q < w.nbits; ++q) L.seed_add(tbl + (size_t)(2 * q) * NV * C, (double)((g0 >> q) & 1u));
-    L.term(false);  // k0 even (b >= 1) or the only term
+    // the first term's sign is the parity of k0 (odd only for one-term
+    // blocks, b = 0); the flips inside a block alternate it
+    L.term((k0 & 1u) != 0);
     for (uint32_t t = 1; t < B; ++t) {
       const int q = __builtin_ctz(t);
       L.apply(row(tbl, q, ((kpar + t) >> (q + 1)) & 1u));
