@@ -570,6 +570,25 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     use_win = plan_ryser_window(masks, N, lanes_max, win_mode == 2, win);
     if (use_win) plan = win.plan;
   }
+  // small square walks: one workgroup stages, walks, reduces and writes the
+  // result in one launch, with no scratch memory
+  if (chunk_log2 < 0 && M == N && nbits <= SMALL_WALK_MAX_BITS && nv <= SMALL_WALK_MAX_NV &&
+      !use_win) {
+    tune_record(1.0);
+    SmallWalk sw;
+    sw.algo = algo;
+    sw.n = N;
+    sw.dt = dt;
+    sw.dA = dA;
+    sw.lda = lda;
+    sw.tr = tr;
+    sw.ot = ot;
+    sw.nonneg = kind == ENGINE_INT && dt == PERM_B8 && algo == 1;
+    profile_begin(s);
+    const hipError_t e = launch_small_walk(kind, sw, dOut, s);
+    profile_end(s);
+    return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+  }
   uint64_t bpl_run = plan.blocks_per_lane;
   const double f = tune_fraction();
   if (f < 1.0 && plan.blocks_per_lane >= 4) {

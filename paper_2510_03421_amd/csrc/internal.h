@@ -59,6 +59,24 @@ struct GrayWalk {
   int wlow = 0, wshift = 0;
 };
 
+// Small square walks in one workgroup (small_walk.hip): Glynn with n - 1
+// and square Ryser with n Gray bits, at most SMALL_WALK_MAX_BITS bits and
+// SMALL_WALK_MAX_NV entries; staging, walk, reduction and normalisation in
+// one launch with no scratch memory.
+#define SMALL_WALK_MAX_BITS 15
+#define SMALL_WALK_MAX_NV 16
+struct SmallWalk {
+  int algo;  // 0 Glynn, 1 square Ryser
+  int n;
+  perm_dtype dt;
+  const void *dA;
+  int64_t lda;
+  int tr;
+  perm_out ot;
+  int nonneg;  // ENGINE_INT: every factor >= 0 (0/1 Ryser)
+};
+hipError_t launch_small_walk(int kind, const SmallWalk &a, void *dOut, hipStream_t s);
+
 // Rectangular Ryser by subset size (see ryser_rect.hip for the layout).
 struct RectWalk {
   const double *colT;      // n columns of m (x C) doubles: colT[(j*m + i)*C + c]

@@ -3,27 +3,12 @@
 // the integer overflow pre-check.
 #include "device_common.h"
 #include "finish_common.h"
+#include "input_read.h"
 #include "internal.h"
 #include "pad_model.h"
 
 namespace permgpu {
 namespace {
-
-// Read logical entry (i, j) of A (m <= n after orientation) as (re, im).
-__device__ __forceinline__ void read_entry(perm_dtype dt, const void *dA, int64_t lda, int tr,
-                                           int i, int j, double &re, double &im) {
-  const int64_t o = tr ? (int64_t)j * lda + i : (int64_t)i * lda + j;
-  im = 0.0;
-  switch (dt) {
-    case PERM_F64: re = ((const double *)dA)[o]; break;
-    case PERM_C128:
-      re = ((const double *)dA)[2 * o];
-      im = ((const double *)dA)[2 * o + 1];
-      break;
-    case PERM_I64: re = (double)((const int64_t *)dA)[o]; break;
-    default: re = ((const uint8_t *)dA)[o] ? 1.0 : 0.0; break;
-  }
-}
 
 // Exponent e of the padding value 2^e of the floating-point Glynn sum on an
 // m x n matrix (m < n), chosen by pad_exponent from the data's mean square.
