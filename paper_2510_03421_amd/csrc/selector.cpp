@@ -36,12 +36,15 @@ void selector_features(int M, int N, perm_dtype dt, double density, float f[kSel
 
 const ThresholdTable &default_table() {
   // Alg. 5's structure with values fitted (coordinate search on mean regret)
-  // to 4000 timed MI355X cases, m in 2..30, n in m..48, f64 / c128 / 0-1:
-  //   n <= 9:  square and n <= 4, or 11 m/n - n + 7 > 0 -> combinatoric, else Glynn;
-  //   n >  9:  m/n > 0.5 -> Glynn, else Ryser (by subset size).
+  // to 4000 timed MI355X cases, m in 2..30, n in m..48, f64 / c128 / 0-1,
+  // the e_m rule and the sweep's rank applied after it (rank_algorithms):
+  //   n <= 2:  square and n <= 4, or -m/n - n + 5.5 > 0 -> combinatoric, else Glynn;
+  //   n >  2:  2 m/n - 0.62 > 0 -> Glynn, else Ryser (by subset size).
+  // (With the e_m form taking most rectangular shapes, the definition's
+  // small-matrix branch no longer pays off.)
   static const ThresholdTable t = {{0.0,
-                                    /*p1*/ 11.0, /*p2*/ -1.0, /*p3*/ 7.0, /*p4*/ 4.0,
-                                    /*p5*/ 1.0, /*p6*/ 0.0, /*p7*/ -0.5, /*p8*/ 9.0}};
+                                    /*p1*/ -1.0, /*p2*/ -1.0, /*p3*/ 5.5, /*p4*/ 4.0,
+                                    /*p5*/ 2.0, /*p6*/ 0.0, /*p7*/ -0.62, /*p8*/ 2.0}};
   return t;
 }
 
