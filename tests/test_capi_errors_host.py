@@ -14,7 +14,8 @@ def no_device():
     return torch.cuda.device_count() == 0
 
 
-ENTRY = ("perm_glynn", "perm_ryser", "perm_combinatoric", "perm_glynn_esym")
+ENTRY = ("perm_glynn", "perm_ryser", "perm_combinatoric", "perm_glynn_esym", "perm_column_sweep",
+         "perm_glynn_noalloc")
 
 
 def call(name, m, n, dt, a, lda, ot, out, flags=0):
@@ -49,7 +50,9 @@ def test_without_a_device_every_entry_point_fails_cleanly():
     o = out.ctypes.data
     for name in ENTRY:
         assert call(name, 4, 6, C.PERM_F64, a.ctypes.data, 6, C.PERM_OUT_F64, o) == C.PERM_E_HIP
-        assert call(name, 4, 6, C.PERM_B8, b.ctypes.data, 6, C.PERM_OUT_I128, o) == C.PERM_E_HIP
+        # the allocation-free variant serves floating-point outputs only
+        want = C.PERM_E_UNSUPPORTED if name == "perm_glynn_noalloc" else C.PERM_E_HIP
+        assert call(name, 4, 6, C.PERM_B8, b.ctypes.data, 6, C.PERM_OUT_I128, o) == want
     ch = ctypes.c_int(-1)
     assert C.lib.perm_auto(4, 6, C.PERM_F64, a.ctypes.data, 6, C.PERM_OUT_F64, o, 0, None, -1.0,
                            ctypes.byref(ch)) == C.PERM_E_HIP
