@@ -594,7 +594,10 @@ def main():
             ref = rec["value"]["hi"] + rec["value"]["lo"]
             pabs = rec["per_abs"]["hi"]
             d = abs(result - ref)
-            err = {"abs_err": d, "rel_err": d / abs(ref), "err_over_per_abs": d / pabs,
+            rel = d / abs(ref)
+            # Sec. 4: digits lost = log10(relative error / machine epsilon), 0 if exact
+            err = {"abs_err": d, "rel_err": rel, "err_over_per_abs": d / pabs,
+                   "digits_lost": max(0.0, math.log10(rel / 2.0 ** -52)) if rel > 0 else 0.0,
                    "criterion_1e-11_per_abs": bool(d <= 1e-11 * pabs)}
 
     achieved = TERMS * FLOPS_PER_TERM / (kernel_ms * 1e-3) / 1e12
@@ -613,11 +616,13 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "glynn_32x32_f64_uniform[-1,1]", "m": N, "n": N, "seed": SEED,
-                   "terms": TERMS, "algorithm": "glynn", "output": "double-double"},
+                   "terms": TERMS, "algorithm": "glynn", "output": "double-double",
+                   "input_sha256_16": hashlib.sha256(a_host.tobytes()).hexdigest()[:16]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_FLOPS / 1e12,
                      "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_FP64_FLOPS,
                      "traffic": profiled_traffic(), "kernel_ms": kernel_ms,
                      "kernel_ms_median": float(np.median(kms)),
+                     "kernel_ms_min": float(np.min(kms)),
                      "frac_ceiling": FLOPS_PER_TERM / (2.0 * INSTR_PER_TERM),
                      "note": "2N = 64 algorithmic FP64 flops per term (N adds, N-1 multiplies, "
                              "1 accumulating add) x 2^31 terms over the Gray-walk engine "
