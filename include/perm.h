@@ -24,10 +24,13 @@
  *    type (see perm_out).  The caller owns dA and dOut; the library never
  *    frees or retains them.
  *  - stream is a hipStream_t (NULL = the default stream).  All device work is
- *    enqueued on it and the call returns without waiting, with one exception:
- *    integer outputs (PERM_OUT_I64 / PERM_OUT_I128) run an overflow pre-check
+ *    enqueued on it and the call returns without waiting, with these
+ *    exceptions: integer outputs (PERM_OUT_I64 / PERM_OUT_I128) run an overflow pre-check
  *    that reads per-row absolute sums back to the host and so synchronises the
- *    stream, unless PERM_FLAG_WRAP is set.
+ *    stream, unless PERM_FLAG_WRAP is set; square perm_ryser with n >= 28
+ *    (and integer square perm_ryser at any n) reads each row's nonzero
+ *    pattern back to plan its column window, and waits again to upload it
+ *    when one is used.
  *  - Temporary device memory (per-workgroup partial sums) is taken from the
  *    stream-ordered allocator and released on the same stream; calls on
  *    different streams do not share scratch memory and may run concurrently.
@@ -207,25 +210,28 @@ int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, pe
  * order over the 2^n column subsets; rectangular: the subsets of each size
  * s <= m in revolving-door order.  Limits: square n <= 48 (floating point)
  * or n <= 40 (integer); rectangular min(m, n) <= 40 and max(m, n) <= 64.
- * Square with an integer output: a row whose nonzeros all lie in a column
- * set U has an empty sum, so a zero term, for every subset that misses
- * them; when sparse rows make this worthwhile (perm_ryser_window_plan), the
- * columns of U go on the top Gray bits and only their states that meet
- * every such row are walked.  The result is the same integer.  The
- * environment variable PERM_RYSER_WINDOW=0 keeps the whole walk; =2 takes
- * a window whenever one prunes any state. */
+ * Square: a row whose nonzeros all lie in a column set U has an empty sum,
+ * so a zero term, for every subset that misses them; when sparse rows make
+ * this worthwhile (perm_ryser_window_plan), the columns of U go on the top
+ * Gray bits and only their states that meet every such row are walked.
+ * Integer outputs always consider it (the same integer results);
+ * floating-point outputs from n = 28 on (the skipped terms are exact zeros,
+ * so only the order of the additions changes; below 28 the extra wait for
+ * the nonzero pattern costs more than the window saves).  The environment variable
+ * PERM_RYSER_WINDOW=0 keeps the whole walk; =2 takes a window whenever one
+ * prunes any state, at any n. */
 int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,
                void *dOut, uint32_t flags, void *stream);
 
 /* perm_ryser_window_plan -- the column window perm_ryser uses for a square
- * n x n integer matrix (host only, no device call).  row_masks: HOST
+ * n x n matrix (host only, no device call).  row_masks: HOST
  * uint64[n], bit j of row i set iff a_ij != 0.  lanes_max: the walk's lane
  * count (a power of two >= 256; the device's is resident workgroups x 256).
  * The window U is grown from the rows with the fewest nonzeros while it
  * holds at most min(16, n - 10) columns, and kept only if the model time
  * of the pruned walk (blocks per lane x block cost) is below 0.8 of the
- * whole walk's (force != 0: whenever it prunes a state).  Returns 1 and fills *fw = |U|, *b = log2 of the block
- * length, *wlow = block-index bits under the window state, *nstates = the
+ * whole walk's (force != 0: whenever it prunes a state).  Returns 1 and
+ * fills *fw = |U|, *b = log2 of the block length, *wlow = block-index bits under the window state, *nstates = the
  * number of states of U that meet every row inside U, col_order (may be
  * NULL; HOST int32[n]: Gray bit q toggles column col_order[q], the window
  * on bits n - fw .. n - 1 in ascending column order) and states (may be

@@ -186,7 +186,7 @@ def select(m: int, n: int, dtype: torch.dtype = torch.float64, density: float = 
 
 
 def ryser_window_plan(row_masks, lanes_max: int, force: bool = False):
-    """The column window square integer ``ryser`` walks for an n x n matrix
+    """The column window square ``ryser`` walks for an n x n matrix
     with nonzero pattern ``row_masks`` (n ints, bit j of row i = a_ij != 0):
     None for the whole walk, else a dict with fw, b, wlow, col_order and
     states (host only).  ``force``: any window that prunes (what

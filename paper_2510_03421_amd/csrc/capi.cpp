@@ -415,6 +415,22 @@ struct RyserWindow {
   GrayPlan plan;
 };
 
+// Each row's nonzero mask (any input type), read back in one round trip.
+static int read_row_masks(int M, int N, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                          std::vector<uint64_t> &out, hipStream_t s) {
+  out.assign(M, 0);
+  uint64_t *d = nullptr;
+  if (hipMallocAsync((void **)&d, sizeof(uint64_t) * (size_t)std::max(M, 1), s) != hipSuccess)
+    return PERM_E_HIP;
+  hipError_t e = launch_row_masks(M, N, dt, dA, lda, tr, d, s);
+  if (e == hipSuccess && M > 0)
+    e = hipMemcpyAsync(out.data(), d, sizeof(uint64_t) * (size_t)M, hipMemcpyDeviceToHost, s);
+  hipError_t e2 = hipFreeAsync(d, s);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? PERM_OK : PERM_E_HIP;
+}
+
 // Relative time of an engine walk: blocks per lane times one block (2^b
 // steps of an update and a product over nv entries, plus the closed-form
 // seed of nbits - b + 1 table rows).
@@ -545,18 +561,24 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
                      : kind == ENGINE_CPLX ? ENGINE_MAX_NV_CPLX
                                            : ENGINE_MAX_NV_INT;
   if (nv > nv_max) return PERM_E_TOO_LARGE;
-  // exact square Ryser over the whole walk: prune the column subsets that
-  // leave a sparse row empty (the nonzero masks come with the pre-check)
-  // PERM_RYSER_WINDOW: 0 = always the whole walk, 2 = a window whenever one
-  // prunes (for tests at orders where the model keeps the whole walk)
+  // square Ryser over the whole walk: prune the column subsets that leave a
+  // sparse row empty.  Integer outputs get the nonzero masks with their
+  // pre-check; floating-point outputs read them (one more wait for the
+  // stream, about 0.1 ms of lost overlap between calls) only from n = 28 on,
+  // where the whole walk takes 0.6 ms or more.  PERM_RYSER_WINDOW: 0 = always
+  // the whole walk, 2 = a window whenever one prunes (for tests at orders
+  // where the model keeps the walk)
   const int win_mode = env_int("PERM_RYSER_WINDOW", 1);
-  const bool try_win = kind == ENGINE_INT && algo == 1 && chunk_log2 < 0 && nbits >= 3 &&
-                       win_mode != 0;
+  const bool try_win = algo == 1 && chunk_log2 < 0 && nbits >= 3 && win_mode != 0 &&
+                       (kind == ENGINE_INT || N >= 28 || win_mode == 2);
   std::vector<uint64_t> masks;
   int pl = 3;
   if (kind == ENGINE_INT) {
     int rc = int_precheck(algo, M, N, dt, dA, lda, tr, ot, flags, s, pl,
                           try_win ? &masks : nullptr);
+    if (rc) return rc;
+  } else if (try_win) {
+    int rc = read_row_masks(M, N, dt, dA, lda, tr, masks, s);
     if (rc) return rc;
   }
   GrayPlan plan;
@@ -565,8 +587,10 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
   RyserWindow win;
   bool use_win = false;
   if (try_win) {
-    const uint64_t lanes_max =
-        pow2_floor((uint64_t)device_cus() * (uint64_t)gray_engine_blocks_per_cu_int(nv) * 256u);
+    const int bpc = kind == ENGINE_REAL   ? gray_engine_blocks_per_cu_real(nv)
+                    : kind == ENGINE_CPLX ? gray_engine_blocks_per_cu_cplx(nv)
+                                          : gray_engine_blocks_per_cu_int(nv);
+    const uint64_t lanes_max = pow2_floor((uint64_t)device_cus() * (uint64_t)bpc * 256u);
     use_win = plan_ryser_window(masks, N, lanes_max, win_mode == 2, win);
     if (use_win) plan = win.plan;
   }

@@ -269,6 +269,9 @@ hipError_t launch_finish(int kind, const void *partials, int count, const Finish
 // doubles), out[2(m+n) .. 2(m+n)+m) each row's nonzero mask (columns < 64).
 hipError_t launch_int_stats(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
                             uint64_t *out, hipStream_t s);
+// out[i] = the nonzero mask of logical row i (columns < 64), any input type.
+hipError_t launch_row_masks(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                            uint64_t *out, hipStream_t s);
 
 // Rectangular Ryser staging (column table and difference columns) and engine.
 hipError_t launch_stage_rect(int m, int n, int l, perm_dtype dt, const void *dA, int64_t lda,

@@ -354,6 +354,28 @@ hipError_t launch_finish(int kind, const void *partials, int count, const Finish
   return hipGetLastError();
 }
 
+// one thread per row: the bit mask of its nonzero entries (real or complex)
+__global__ void row_masks_kernel(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                                 uint64_t *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint64_t mask = 0;
+  for (int j = 0; j < n && j < 64; ++j) {
+    double re, im;
+    read_entry(dt, dA, lda, tr, i, j, re, im);
+    if (re != 0.0 || im != 0.0) mask |= 1ull << j;
+  }
+  out[i] = mask;
+}
+
+hipError_t launch_row_masks(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
+                            uint64_t *out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(row_masks_kernel, dim3((m + 63) / 64), dim3(64), 0, s, m, n, dt, dA, lda, tr,
+                     out);
+  return hipGetLastError();
+}
+
 hipError_t launch_int_stats(int m, int n, perm_dtype dt, const void *dA, int64_t lda, int tr,
                             uint64_t *out, hipStream_t s) {
   const int count = m + n;

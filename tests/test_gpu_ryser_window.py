@@ -97,3 +97,44 @@ def test_strided_input():
     view = big.cuda()[:, :20]
     assert view.stride() == (27, 1)
     assert pg.ryser(view).value() == want
+
+
+@pytest.mark.parametrize("n,p,seed", [(24, 0.15, 1), (28, 0.15, 2), (30, 0.15, 3)])
+def test_floating_point_window(n, p, seed):
+    """Floating-point square Ryser takes the window from n = 28 on (forced
+    at 24): the skipped terms are exact zeros, so it agrees with the whole
+    walk to rounding (and, at 24, with the oracle); real and complex."""
+    import paper_2510_03421_amd as pg
+    rng = np.random.default_rng(8100 + seed)
+    pat = rng.random((n, n)) < p
+    pat[np.arange(n), rng.permutation(n)] = True        # a perfect matching: per != 0
+    a = np.where(pat, rng.uniform(-1, 1, size=(n, n)), 0.0)
+    assert pg.ryser_window_plan(masks_of(a), 1 << 18) is not None
+    mode = "2" if n < 28 else "1"
+    got = with_mode(mode, lambda: pg.ryser(dev(a), out="dd").value())
+    whole = whole_walk(lambda: pg.ryser(dev(a), out="dd").value())
+    # per(|A|) <= prod_i sum_j |a_ij|: a certified scale for the criterion
+    # where the oracle's per(|A|) is out of reach
+    rows_bound = float(np.prod(np.abs(a).sum(axis=1)))
+    if n <= 24:
+        scale = float(oracle.per_laplace(np.abs(a)).hi)
+        want = oracle.per_laplace(a)
+        assert abs((got[0] + got[1]) - (want.hi + want.lo)) <= 1e-11 * scale
+        assert abs((whole[0] + whole[1]) - (want.hi + want.lo)) <= 1e-11 * scale
+    assert abs((got[0] + got[1]) - (whole[0] + whole[1])) <= 1e-11 * rows_bound
+    assert got[0] != 0.0
+    c = a * np.exp(1j * rng.uniform(0, 2 * np.pi, size=(n, n)))
+    gc = with_mode(mode, lambda: pg.ryser(dev(c)).value())
+    wc = whole_walk(lambda: pg.ryser(dev(c)).value())
+    assert abs(gc - wc) <= 1e-11 * float(np.prod(np.abs(c).sum(axis=1)))
+    assert gc != 0
+
+
+def test_floating_point_window_forced_small():
+    """The forced window at n = 14 on real input against the oracle."""
+    import paper_2510_03421_amd as pg
+    a = sparse(14, 0.25, 8200).astype(np.float64) * workloads.uniform(14, 14, 8201)
+    want = oracle.per_laplace(a)
+    scale = float(oracle.per_laplace(np.abs(a)).hi)
+    got = with_mode("2", lambda: pg.ryser(dev(a), out="dd").value())
+    assert abs((got[0] + got[1]) - (want.hi + want.lo)) <= 1e-11 * scale
