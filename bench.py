@@ -48,19 +48,25 @@ INSTR_PER_TERM = 2 * N - 1
 def profiled_traffic():
     """HBM bytes per engine launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, or None if the kernel sources changed since."""
+    return profiled_value("traffic_bytes_per_launch")
+
+
+def profiled_value(key: str):
+    """A `key: value` figure of the committed headline-kernel profile, or None
+    if the kernel sources changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "glynn32_f64_engine.txt")
     if not os.path.exists(path):
         return None
     src = os.path.join(ROOT, "paper_2510_03421_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("gray_engine.inc", "device_common.h"):
+    for f in ("gray_engine.inc", "gray_lanes.h", "device_common.h"):
         h.update(open(os.path.join(src, f), "rb").read())
     text = open(path).read()
     if f"kernel_source_sha256_16: {h.hexdigest()[:16]}" not in text:
         return None
     for line in text.splitlines():
-        if line.startswith("traffic_bytes_per_launch:"):
+        if line.startswith(key + ":"):
             return float(line.split(":")[1])
     return None
 
@@ -104,9 +110,18 @@ def environment():
     except OSError:
         pass
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    mem_gib = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                mem_gib = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
     return {"gpu": torch.cuda.get_device_name(0), "hip": torch.version.hip,
             "torch": torch.__version__, "library_version": pg.version(),
-            "host_cpu": cpu, "host_threads": threads}
+            "host_cpu": cpu, "host_threads": threads, "host_cpus_online": os.cpu_count(),
+            "host_mem_gib": mem_gib}
 
 
 def _terms(algo, m, n):
@@ -638,6 +653,10 @@ def main():
                                "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz"},
         "result": result,
         "error_vs_oracle": err,
+        # shader clock the engine ran at in the committed profile of this
+        # kernel (GRBM_GUI_ACTIVE cycles per XCD over its duration); the peaks
+        # above assume 2.4 GHz
+        "sclk_ghz_profiled": profiled_value("clock_ghz"),
     }
     if not args.no_batched:
         # the metric's second part: batched permanents per second (one graph
