@@ -27,10 +27,11 @@
  *    enqueued on it and the call returns without waiting, with these
  *    exceptions: integer outputs (PERM_OUT_I64 / PERM_OUT_I128) run an overflow pre-check
  *    that reads per-row absolute sums back to the host and so synchronises the
- *    stream, unless PERM_FLAG_WRAP is set; square perm_ryser with n >= 28
- *    (and integer square perm_ryser at any n) reads each row's nonzero
- *    pattern back to plan its column window, and waits again to upload it
- *    when one is used.
+ *    stream, unless PERM_FLAG_WRAP is set; square floating-point
+ *    perm_ryser with n >= 30 (complex: n >= 29) or PERM_FLAG_SPARSE, and
+ *    integer square perm_ryser at any n, read each row's nonzero pattern
+ *    back to plan a column window, and wait again to upload it when one is
+ *    used.
  *  - Temporary device memory (per-workgroup partial sums) is taken from the
  *    stream-ordered allocator and released on the same stream; calls on
  *    different streams do not share scratch memory and may run concurrently.
@@ -116,6 +117,10 @@ typedef enum perm_algo {
 #define PERM_BATCH_AUTOTUNE 0x4u /* perm_batch_plan_create: choose the matrices per
                                     wave of every small order by timing on the
                                     plan's first run (see perm_batch_plan_run) */
+#define PERM_FLAG_SPARSE 0x8u /* square perm_ryser, floating point: read the
+                                 nonzero pattern back and plan a column window at
+                                 any order (see perm_ryser; one more wait for the
+                                 stream) */
 
 /* Library version, PERM_VERSION. */
 int perm_version(void);
@@ -215,9 +220,11 @@ int perm_glynn_esym(int m, int n, perm_dtype dt, const void *dA, int64_t lda, pe
  * this worthwhile (perm_ryser_window_plan), the columns of U go on the top
  * Gray bits and only their states that meet every such row are walked.
  * Integer outputs always consider it (the same integer results);
- * floating-point outputs from n = 28 on (the skipped terms are exact zeros,
- * so only the order of the additions changes; below 28 the extra wait for
- * the nonzero pattern costs more than the window saves).  The environment variable
+ * floating-point outputs when the whole walk is long, n >= 30 (complex:
+ * n >= 29), or at any n with PERM_FLAG_SPARSE (the skipped terms are exact
+ * zeros, so only the order of the additions changes; the extra wait for the
+ * nonzero pattern, about 0.1 ms per call of lost overlap, is under 6% of a
+ * dense walk from those orders on).  The environment variable
  * PERM_RYSER_WINDOW=0 keeps the whole walk; =2 takes a window whenever one
  * prunes any state, at any n. */
 int perm_ryser(int m, int n, perm_dtype dt, const void *dA, int64_t lda, perm_out ot,

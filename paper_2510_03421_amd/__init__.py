@@ -128,7 +128,10 @@ def glynn(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:
 
 
 def ryser(a: torch.Tensor, out: str | None = None, flags: int = 0) -> Result:
-    """Ryser's formula (square; rectangular by subset size)."""
+    """Ryser's formula (square; rectangular by subset size).  Square sparse
+    input skips the column subsets that leave a row empty (a column window;
+    floating point from n = 30, complex 29, or at any n with
+    flags=PERM_FLAG_SPARSE)."""
     return _run(C.lib.perm_ryser, a, out, flags)
 
 

@@ -30,6 +30,7 @@ PERM_ALGO_COMBINATORIC, PERM_ALGO_RYSER, PERM_ALGO_GLYNN, PERM_ALGO_GLYNN_ESYM, 
 PERM_FLAG_WRAP = 0x1
 PERM_FLAG_PAD_ONES = 0x2
 PERM_BATCH_AUTOTUNE = 0x4
+PERM_FLAG_SPARSE = 0x8
 PERM_NOALLOC_SCRATCH_BYTES = 256 * 1024
 
 _i32, _i64, _u32, _p, _d = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, \

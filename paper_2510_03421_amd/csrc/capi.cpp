@@ -564,13 +564,16 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
   // square Ryser over the whole walk: prune the column subsets that leave a
   // sparse row empty.  Integer outputs get the nonzero masks with their
   // pre-check; floating-point outputs read them (one more wait for the
-  // stream, about 0.1 ms of lost overlap between calls) only from n = 28 on,
-  // where the whole walk takes 0.6 ms or more.  PERM_RYSER_WINDOW: 0 = always
-  // the whole walk, 2 = a window whenever one prunes (for tests at orders
-  // where the model keeps the walk)
+  // stream, about 0.1 ms of lost overlap between calls) when the caller says
+  // the input is sparse, or when the whole walk takes 2 ms or more (real
+  // n >= 30, complex n >= 29), where that wait costs a dense input under 6%.
+  // PERM_RYSER_WINDOW: 0 = always the whole walk, 2 = a window whenever one
+  // prunes (for tests at orders where the model keeps the walk)
   const int win_mode = env_int("PERM_RYSER_WINDOW", 1);
+  const bool fp_long = (kind == ENGINE_REAL && N >= 30) || (kind == ENGINE_CPLX && N >= 29);
   const bool try_win = algo == 1 && chunk_log2 < 0 && nbits >= 3 && win_mode != 0 &&
-                       (kind == ENGINE_INT || N >= 28 || win_mode == 2);
+                       (kind == ENGINE_INT || fp_long || (flags & PERM_FLAG_SPARSE) != 0 ||
+                        win_mode == 2);
   std::vector<uint64_t> masks;
   int pl = 3;
   if (kind == ENGINE_INT) {

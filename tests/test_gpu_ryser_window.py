@@ -101,18 +101,20 @@ def test_strided_input():
 
 @pytest.mark.parametrize("n,p,seed", [(24, 0.15, 1), (28, 0.15, 2), (30, 0.15, 3)])
 def test_floating_point_window(n, p, seed):
-    """Floating-point square Ryser takes the window from n = 28 on (forced
-    at 24): the skipped terms are exact zeros, so it agrees with the whole
-    walk to rounding (and, at 24, with the oracle); real and complex."""
+    """Floating-point square Ryser takes the window by itself from n = 30
+    (complex 29) and at any n with PERM_FLAG_SPARSE: the skipped terms are
+    exact zeros, so it agrees with the whole walk to rounding (and, at 24,
+    with the oracle); real and complex."""
     import paper_2510_03421_amd as pg
+    from paper_2510_03421_amd import _capi as C
     rng = np.random.default_rng(8100 + seed)
     pat = rng.random((n, n)) < p
     pat[np.arange(n), rng.permutation(n)] = True        # a perfect matching: per != 0
     a = np.where(pat, rng.uniform(-1, 1, size=(n, n)), 0.0)
     assert pg.ryser_window_plan(masks_of(a), 1 << 18) is not None
-    mode = "2" if n < 28 else "1"
-    got = with_mode(mode, lambda: pg.ryser(dev(a), out="dd").value())
-    whole = whole_walk(lambda: pg.ryser(dev(a), out="dd").value())
+    fl = C.PERM_FLAG_SPARSE if n < 30 else 0
+    got = pg.ryser(dev(a), out="dd", flags=fl).value()
+    whole = whole_walk(lambda: pg.ryser(dev(a), out="dd", flags=fl).value())
     # per(|A|) <= prod_i sum_j |a_ij|: a certified scale for the criterion
     # where the oracle's per(|A|) is out of reach
     rows_bound = float(np.prod(np.abs(a).sum(axis=1)))
@@ -124,7 +126,7 @@ def test_floating_point_window(n, p, seed):
     assert abs((got[0] + got[1]) - (whole[0] + whole[1])) <= 1e-11 * rows_bound
     assert got[0] != 0.0
     c = a * np.exp(1j * rng.uniform(0, 2 * np.pi, size=(n, n)))
-    gc = with_mode(mode, lambda: pg.ryser(dev(c)).value())
+    gc = pg.ryser(dev(c), flags=C.PERM_FLAG_SPARSE if n < 29 else 0).value()
     wc = whole_walk(lambda: pg.ryser(dev(c)).value())
     assert abs(gc - wc) <= 1e-11 * float(np.prod(np.abs(c).sum(axis=1)))
     assert gc != 0
