@@ -159,6 +159,27 @@ int plan_gray_bpc(int bpc, int nbits, GrayPlan &p, int min_b) {
   return PERM_OK;
 }
 
+// The paired real walk's plan (two blocks per lane at a time): blocks of 2^b
+// steps, 3 <= b <= 12, and four or more blocks per lane on every lane the
+// paired kernel keeps resident; false when the walk is too short to fill them.
+static bool plan_gray_pair(int nv, int nbits, GrayPlan &p) {
+  const int bpc = gray_engine_blocks_per_cu_real_pair(nv);
+  const int cus = device_cus();
+  if (bpc <= 0 || cus <= 0) return false;
+  const uint64_t lanes = pow2_floor((uint64_t)cus * (uint64_t)bpc * 256u);
+  const int lg = ilog2(lanes);
+  int b = std::min(nbits - lg - 2, 12);
+  const int bo = env_int("PERM_BLOCK_LOG2", -1);
+  if (bo >= 0) b = bo;
+  if (b < 3 || nbits - b < lg + 2) return false;
+  p.b = b;
+  p.lanes = lanes;
+  p.blocks_per_lane = 1ull << (nbits - b - lg);
+  p.block = 256;
+  p.grid = (int)(lanes / 256u);
+  return true;
+}
+
 // VALU operations of one e_m term on an n-vector (degree m): the n updates
 // and the recurrence -- its band for the exact-degree kernels, every degree
 // up to min(n, 32) plus the run-time pick of e_m for the generic ones; a
@@ -616,12 +637,24 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
     profile_end(s);
     return e == hipSuccess ? PERM_OK : PERM_E_HIP;
   }
+  // real walks without a window: the paired kernel (one scalar row load for
+  // two blocks) wherever it fills the device
+  bool pair = false;
+  if (kind == ENGINE_REAL && !use_win && env_int("PERM_ENGINE_PAIR", 1) != 0) {
+    GrayPlan pp;
+    if (plan_gray_pair(nv, nbits, pp)) {
+      plan = pp;
+      pair = true;
+    }
+  }
   uint64_t bpl_run = plan.blocks_per_lane;
   const double f = tune_fraction();
   if (f < 1.0 && plan.blocks_per_lane >= 4) {
-    // keep an even count: the engine pairs blocks of opposite parity
-    bpl_run = (uint64_t)std::llround((double)plan.blocks_per_lane * f / 2.0) * 2;
-    bpl_run = std::max<uint64_t>(2, std::min(bpl_run, plan.blocks_per_lane));
+    // keep an even count (the engine pairs blocks of opposite parity), a
+    // multiple of 4 for the paired kernel
+    const uint64_t unit = pair ? 4 : 2;
+    bpl_run = (uint64_t)std::llround((double)plan.blocks_per_lane * f / (double)unit) * unit;
+    bpl_run = std::max<uint64_t>(unit, std::min(bpl_run, plan.blocks_per_lane));
   }
   tune_record((double)bpl_run / (double)plan.blocks_per_lane);
   const int C = kind == ENGINE_CPLX ? 2 : 1;
@@ -688,7 +721,10 @@ int run_gray(int algo, int M, int N, perm_dtype dt, const void *dA, int64_t lda,
       e = launch_gray_tiny(kind, w, part, s);
     } else {
       switch (kind) {
-        case ENGINE_REAL: e = launch_gray_engine_real(w, plan.grid, plan.block, part, s); break;
+        case ENGINE_REAL:
+          e = pair ? launch_gray_engine_real_pair(w, plan.grid, plan.block, part, s)
+                   : launch_gray_engine_real(w, plan.grid, plan.block, part, s);
+          break;
         case ENGINE_CPLX: e = launch_gray_engine_cplx(w, plan.grid, plan.block, part, s); break;
         default: e = launch_gray_engine_int(w, plan.grid, plan.block, part, s); break;
       }

@@ -11,6 +11,8 @@ int gray_occ_real_b(int nv);
 hipError_t gray_launch_real_b(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
 int gray_occ_real_c(int nv);
 hipError_t gray_launch_real_c(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
+int gray_occ_real_pair(int nv);
+hipError_t gray_launch_real_pair(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
 int gray_occ_cplx_a(int nv);
 hipError_t gray_launch_cplx_a(const GrayWalk &w, int grid, int block, void *partials, hipStream_t s);
 int gray_occ_cplx_b(int nv);
@@ -38,6 +40,19 @@ hipError_t launch_gray_engine_real(const GrayWalk &w, int grid, int block, void 
   if (w.nv >= 1 && w.nv <= 24) return gray_launch_real_a(w, grid, block, partials, s);
   if (w.nv >= 25 && w.nv <= 40) return gray_launch_real_b(w, grid, block, partials, s);
   if (w.nv >= 41 && w.nv <= 48) return gray_launch_real_c(w, grid, block, partials, s);
+  return hipErrorInvalidValue;
+}
+
+int gray_engine_blocks_per_cu_real_pair(int nv) {
+  if (nv >= GRAY_PAIR_MIN_NV && nv <= GRAY_PAIR_MAX_NV) return gray_occ_real_pair(nv);
+  return 0;
+}
+
+hipError_t launch_gray_engine_real_pair(const GrayWalk &w, int grid, int block, void *partials,
+                                        hipStream_t s) {
+  if (w.nv >= GRAY_PAIR_MIN_NV && w.nv <= GRAY_PAIR_MAX_NV && !w.wlist && w.b >= 3 &&
+      w.blocks_per_lane % 4 == 0)
+    return gray_launch_real_pair(w, grid, block, partials, s);
   return hipErrorInvalidValue;
 }
 

@@ -15,6 +15,9 @@ constexpr int kMaxN = 64;        // largest side accepted by any path
 #define ENGINE_MAX_NV_REAL 48
 #define ENGINE_MAX_NV_CPLX 48
 #define ENGINE_MAX_NV_INT 40
+// Vector lengths of the paired real walk (two blocks per lane at a time).
+#define GRAY_PAIR_MIN_NV 16
+#define GRAY_PAIR_MAX_NV 32
 #ifndef RECT_MAX_M
 #define RECT_MAX_M 40
 #endif
@@ -236,6 +239,12 @@ hipError_t launch_gray_tiny(int kind, const GrayWalk &w, void *partials, hipStre
 int gray_engine_blocks_per_cu_real(int nv);
 int gray_engine_blocks_per_cu_cplx(int nv);
 int gray_engine_blocks_per_cu_int(int nv);
+// The paired real walk: GRAY_PAIR_MIN_NV <= w.nv <= GRAY_PAIR_MAX_NV, no
+// column window, w.b >= 3 and w.blocks_per_lane a multiple of 4 (the caller
+// guarantees them); partials as launch_gray_engine_real.
+hipError_t launch_gray_engine_real_pair(const GrayWalk &w, int grid, int block, void *partials,
+                                        hipStream_t s);
+int gray_engine_blocks_per_cu_real_pair(int nv);
 
 // The e_m form of the rectangular Glynn sum (esym.inc): the walk over the
 // signs of rows 1..m-1 with the n column sums as its vector (w.nv = n,
