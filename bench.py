@@ -649,7 +649,7 @@ def main():
         "fp64_issue": {"achieved": issue, "peak": PEAK_FP64_ISSUE / 1e12,
                        "unit": "T FP64 lane-instructions/s", "frac": issue * 1e12 / PEAK_FP64_ISSUE,
                        "note": "63 FP64 VALU instructions per term (algorithmic; the counters "
-                               "measure 64.07 with re-seeds and compensated folds) against "
+                               "measure 64.04 with re-seeds and compensated folds) against "
                                "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz"},
         "result": result,
         "error_vs_oracle": err,
