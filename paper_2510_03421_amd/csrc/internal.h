@@ -17,7 +17,7 @@ constexpr int kMaxN = 64;        // largest side accepted by any path
 #define ENGINE_MAX_NV_INT 40
 // Vector lengths of the paired real walk (two blocks per lane at a time).
 #define GRAY_PAIR_MIN_NV 16
-#define GRAY_PAIR_MAX_NV 32
+#define GRAY_PAIR_MAX_NV 40
 #ifndef RECT_MAX_M
 #define RECT_MAX_M 40
 #endif

@@ -1,5 +1,5 @@
 """The paired real walk (two Gray blocks per lane at a time, one scalar row
-load for both; used for real walks of 16..32 entries that fill the device)
+load for both; used for real walks of 16..40 entries that fill the device)
 against the oracle and against the single walk (PERM_ENGINE_PAIR=0): square
 Glynn and Ryser, rectangular Glynn.  (Chunks of the 32 x 32 sum, which take
 the paired walk too, are covered by test_gpu_chunks.py.)"""
