@@ -89,3 +89,30 @@ def test_selector_file_errors(lib, tmp_path):
     bad.write_text("not-a-selector 1\n")
     assert lib.perm_selector_load(str(bad).encode()) == -1
     assert lib.perm_selector_load(None) == 0
+
+
+def header_constants():
+    """Every enum value and integer #define of include/perm.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    consts = {k: int(v) for k, v in re.findall(r"\b(PERM_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    for k, v in re.findall(r"#define\s+(PERM_[A-Z0-9_]+)\s+(.+)", text):
+        # integer literals, or a product of them in parentheses
+        factors = v.strip().strip("()").split("*")
+        lits = [re.fullmatch(r"\s*(0x[0-9a-fA-F]+|\d+)u?\s*", f) for f in factors]
+        if all(lits):
+            value = 1
+            for m in lits:
+                value *= int(m.group(1), 0)
+            consts[k] = value
+    return consts
+
+
+def test_binding_constants_match_the_header():
+    """The Python binding's copies of the enums and flags equal the header's."""
+    from paper_2510_03421_amd import _capi as C
+    consts = header_constants()
+    assert consts["PERM_FLAG_SPARSE"] == 0x8 and consts["PERM_E_UNSUPPORTED"] == -5
+    shared = [k for k in consts if hasattr(C, k)]
+    assert len(shared) >= 25
+    for k in shared:
+        assert getattr(C, k) == consts[k], k
